@@ -1,0 +1,102 @@
+"""Oracle end-to-end render and gradients for one scene and one view.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Forward: ``preprocess`` (fp64 torch) -> records -> per-pixel compositing in
+plain C (no tiles).  Gradients: the C adjoint gives d loss / d record, and
+torch's fp64 autograd carries it back through the per-primitive steps.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import preprocess as pp
+from . import raster
+
+# relative bands for per-primitive decisions that fp32 may take differently
+BAND_NEAR = 1e-5     # depth vs the near plane
+BAND_OPACITY = 1e-4  # o(q) vs 1/255
+BAND_DET = 1e-6      # det(Sigma') / (Sigma'_00 Sigma'_11) vs 0
+
+# record columns that receive a compositing gradient (d_rec order)
+_GRAD_COLS = [0, 1, 2, 3, 4, 6, 7, 8, 9, 10]
+
+
+def ambiguous_records(out: dict) -> np.ndarray:
+    """Primitives whose culling decision sits within a band of a threshold."""
+    depth = out["depth"].detach().numpy()
+    o_q = out["o_q"].detach().numpy()
+    Sp = out["Sp"].detach().numpy()
+    det = Sp[:, 0, 0] * Sp[:, 1, 1] - Sp[:, 0, 1] * Sp[:, 1, 0]
+    scale = np.abs(Sp[:, 0, 0] * Sp[:, 1, 1]) + 1e-300
+    amb = (np.abs(depth - pp.NEAR_PLANE) <= BAND_NEAR * pp.NEAR_PLANE)
+    amb |= (np.abs(o_q * 255.0 - 1.0) <= BAND_OPACITY)
+    amb |= (np.abs(det) / scale <= BAND_DET) & (depth > pp.NEAR_PLANE)
+    return amb
+
+
+def _amb_records(out: dict, amb: np.ndarray) -> np.ndarray:
+    """Records with the would-be splat of each ambiguous-but-culled primitive
+    (rho = 0: never contributes, only flags the pixels it could touch)."""
+    rec = out["rec"].detach().numpy().copy()
+    idx = np.flatnonzero(amb & ~out["valid"].numpy())
+    if idx.size:
+        Sp = out["Sp"].detach().numpy()[idx]
+        m2 = out["mean2d"].detach().numpy()[idx]
+        det = Sp[:, 0, 0] * Sp[:, 1, 1] - Sp[:, 0, 1] ** 2
+        ok = det > 0
+        dets = np.where(ok, det, 1.0)
+        rec[idx, 0] = m2[:, 0]
+        rec[idx, 1] = m2[:, 1]
+        rec[idx, 2] = np.where(ok, Sp[:, 1, 1] / dets, 0.0)   # det <= 0: flags everything
+        rec[idx, 3] = np.where(ok, -Sp[:, 0, 1] / dets, 0.0)
+        rec[idx, 4] = np.where(ok, Sp[:, 0, 0] / dets, 0.0)
+        rec[idx, 5] = 0.0
+    return rec
+
+
+def render(params: np.ndarray, dim: int, rot: int, view, *, d_image: Optional[np.ndarray] = None,
+           d_tfinal: Optional[np.ndarray] = None, l1_target: Optional[np.ndarray] = None,
+           rows=None, bands=raster.DEFAULT_BANDS):
+    """Render one view in float64.
+
+    params: [F][n] (any float dtype; promoted to float64).  If ``d_image``
+    (or ``l1_target``: L1-mean loss against it, sign(0) = 0) is given, also
+    returns ``dparams`` [F][n].
+    """
+    want_grad = d_image is not None or l1_target is not None
+    P = torch.tensor(np.asarray(params, dtype=np.float64), requires_grad=want_grad)
+    out = pp.preprocess(P, dim, rot, view)
+    rec = out["rec"].detach().numpy()
+    amb = ambiguous_records(out)
+    rec_f = _amb_records(out, amb) if amb.any() else rec
+    W, H = view.width, view.height
+    img, tf, nc, fl = raster.render_fwd(rec_f, W, H, amb=amb if amb.any() else None,
+                                        rows=rows, bands=bands)
+    res = {"image": img, "t_final": tf, "ncontrib": nc, "flags": fl, "rec": rec,
+           "valid": out["valid"].numpy(), "amb": amb, "out": out}
+    if want_grad:
+        if l1_target is not None:
+            d_image = np.sign(img - l1_target) / float(img.size)
+            res["loss"] = float(np.abs(img - l1_target).mean())
+        d_rec = raster.render_bwd(rec, W, H, d_image, d_tfinal)
+        G = np.zeros_like(rec)
+        G[:, _GRAD_COLS] = d_rec
+        torch.autograd.backward(out["rec"], torch.from_numpy(G))
+        res["dparams"] = P.grad.numpy().copy()
+        res["d_rec"] = d_rec
+        res["d_image"] = d_image
+    return res
+
+
+def loss_value(params: np.ndarray, dim: int, rot: int, view, weight_image: np.ndarray,
+               weight_t: Optional[np.ndarray] = None) -> float:
+    """Scalar <weight_image, image> + <weight_t, T_final> for finite differences."""
+    r = render(params, dim, rot, view)
+    v = float((r["image"] * weight_image).sum())
+    if weight_t is not None:
+        v += float((r["t_final"] * weight_t).sum())
+    return v
