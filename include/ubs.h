@@ -1,0 +1,290 @@
+/*
+ * ubs.h -- C ABI of the MI355X (gfx950) Universal Beta Splatting renderer.
+ *
+ * The library renders N-dimensional anisotropic Beta primitives (the
+ * paper's Section 4: N = 3 + C with C query dimensions; C = 0 static 3-D,
+ * C = 3 view direction "UBS-6D", C = 4 time + view direction "UBS-7D")
+ * through a differentiable tile rasteriser, and returns the gradient of a
+ * loss with respect to every primitive parameter.
+ *
+ * A frame is four calls on one HIP stream, in this order:
+ *   ubs_preprocess  condition each primitive on the view's query, project
+ *                   it to a screen-space splat record (Section 4.2-4.3,
+ *                   Section 3 projection);
+ *   ubs_bin_sort    emit one (tile, depth) key per overlapped tile, radix
+ *                   sort the keys, find each tile's range;
+ *   ubs_render_fwd  alpha-composite each tile front to back (Section 3
+ *                   compositing with the Beta kernel of Section 4.3);
+ *   ubs_render_bwd  adjoint of the two previous steps: gradient of the loss
+ *                   with respect to every primitive parameter.
+ *
+ * Conventions shared by every entry point
+ *   - All array pointers are DEVICE pointers owned by the caller.  The
+ *     library allocates no device memory and keeps no state between calls
+ *     other than what it writes into the caller's workspace `ws`.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls only
+ *     enqueue work; none synchronises the stream.  All four calls of a frame
+ *     must use the same frame description, the same `ws`, and be ordered on
+ *     one stream (or synchronised by the caller).
+ *   - Argument errors are detected on the host before any launch and
+ *     returned synchronously; nothing is enqueued in that case.  Conditions
+ *     discovered on the device (too many tile pairs, non-finite parameters)
+ *     are written to the status block at the head of `ws` (ubs_status_block)
+ *     and can be read after the stream has been synchronised.
+ *   - Calls on distinct workspaces are independent and may run concurrently
+ *     on different streams.  The calls are safe to capture into a HIP graph
+ *     (no host synchronisation, no memset/memcpy nodes).
+ */
+#ifndef UBS_H
+#define UBS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UBS_ABI_VERSION 1
+#define UBS_MAX_QUERY_DIMS 4  /* C <= 4: N <= 7 */
+#define UBS_MAX_VIEWS 4096
+#define UBS_MAX_SCENES 256
+
+typedef enum {
+  UBS_OK = 0,
+  UBS_ERR_ARG = 1,          /* invalid argument (null pointer, size, enum) */
+  UBS_ERR_UNSUPPORTED = 2,  /* valid but unsupported (e.g. C > 4, tile shape) */
+  UBS_ERR_CAPACITY = 3,     /* workspace too small for the frame */
+  UBS_ERR_HIP = 4           /* a HIP runtime call failed */
+} ubs_status;
+
+/* Spatial rotation parameterisation (Section 4.2 and its appendix). */
+typedef enum {
+  UBS_ROT_QUAT = 0,  /* unit quaternion (w, x, y, z), normalised in-kernel   */
+  UBS_ROT_SKEW = 1   /* first-order Taylor R = I + A(w), A skew-symmetric    */
+} ubs_rot;
+
+/*
+ * A scene: n primitives of dimension dim = 3 + C (0 <= C <= 4).
+ *
+ * params: float32 [F][n], component-major (row r holds component r of every
+ * primitive, primitive i at params[r * n + i]).  Rows, in order:
+ *   mu_x     3          spatial mean (world units)
+ *   mu_q     C          query mean; for C = 4 the order is [t, d0, d1, d2]
+ *   rot      4 | 3      quaternion (w,x,y,z) | skew vector w
+ *   log_s_x  3          log spatial scales (s_x = exp)
+ *   L_qx     3C         the C x 3 block L_qx, row-major
+ *   L_q      C(C+1)/2   lower triangle of L_q, row-major, diagonal stored
+ *                       as log scales (diag = exp), strictly-lower free
+ *   b_x      1          spatial Beta shape, beta_x = 4 exp(b_x)
+ *   b_q      C          query Beta shapes, beta_qi = exp(b_qi)
+ *   o        1          opacity in [0, 1] (already activated)
+ *   rgb      3          colour (already activated)
+ * F = 3 + C + (4|3) + 3 + 3C + C(C+1)/2 + 1 + C + 1 + 3
+ *   (35 for UBS-6D and 44 for UBS-7D with the skew rotation; +1 with quats).
+ * The covariance is Sigma = L L^T with L = [[R_x diag(s_x), 0], [L_qx, L_q]].
+ *
+ * dparams: float32 [F][n] in the same layout; ubs_render_bwd OVERWRITES it
+ * with d loss / d params (it is not accumulated into).  May be NULL for
+ * calls other than ubs_render_bwd.  Must not alias params.
+ */
+typedef struct {
+  int32_t dim;            /* 3..7 */
+  int32_t rot;            /* ubs_rot */
+  int64_t n;              /* number of primitives, >= 0 */
+  const float* params;    /* device [F][n] */
+  float* dparams;         /* device [F][n] or NULL */
+} ubs_scene;
+
+/*
+ * A view: pinhole camera, OpenCV axes (x right, y down, z forward).
+ *   camera point p = R * x_world + t (R row-major 3x3);
+ *   pixel (u, v) = (fx p_x / p_z + cx, fy p_y / p_z + cy);
+ *   pixel (i, j) covers [i, i+1) x [j, j+1), sampled at its centre
+ *   (i + 0.5, j + 0.5).
+ * The query of a primitive in this view is q = d (C = 3) or q = [time, d]
+ * (C = 4), where d is the unit direction from the camera centre -R^T t to
+ * the primitive's spatial mean (world frame).  time is ignored unless C = 4.
+ */
+typedef struct {
+  int32_t scene;          /* index into the scene array */
+  int32_t width, height;  /* pixels, >= 1 */
+  int32_t _pad0;
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float time;
+  float _pad1[3];
+} ubs_view;               /* 96 bytes */
+
+/*
+ * Tuning.  tile_w x tile_h in {8x8, 16x8, 16x16, 32x16}; batch_depth in
+ * {64, 128, 256, 512} (records staged per LDS batch, rounded to the tile's
+ * pixel count); digit_bits in [4, 11] (radix-sort digit width).
+ * pair_capacity: number of (tile, primitive) pairs the workspace holds; if a
+ * frame needs more, ubs_bin_sort sets the status overflow flag, emits no
+ * pairs and the render calls draw nothing (rerun with a larger capacity,
+ * see ubs_status_block.pairs_needed).  flags: UBS_TUNE_* bits.
+ */
+#define UBS_TUNE_PERSISTENT 1u  /* raster through a persistent work queue */
+#define UBS_TUNE_PRE_FP32 2u    /* per-primitive math in float32 (default float64) */
+typedef struct {
+  int32_t tile_w, tile_h;
+  int32_t batch_depth;
+  int32_t digit_bits;
+  int64_t pair_capacity;
+  uint32_t flags;
+  int32_t _pad;
+} ubs_tuning;
+
+/*
+ * Optional per-stage timing.  If ubs_frame.stage_events is non-NULL it points
+ * to 2 * UBS_N_STAGES hipEvent_t handles created by the caller; the library
+ * records event [2 s] before and [2 s + 1] after the kernels of stage s on
+ * the call's stream (the caller reads them with hipEventElapsedTime).  Stages
+ * a call does not run are not recorded.  Nothing else changes.
+ */
+enum {
+  UBS_STAGE_PREPROCESS = 0,   /* ubs_preprocess: per-primitive kernel        */
+  UBS_STAGE_BIN_COUNT = 1,    /* ubs_bin_sort: tile counts                    */
+  UBS_STAGE_SCAN = 2,         /* ubs_bin_sort: exclusive scan of the counts   */
+  UBS_STAGE_BIN_EMIT = 3,     /* ubs_bin_sort: key/value emission             */
+  UBS_STAGE_SORT = 4,         /* ubs_bin_sort: all radix passes               */
+  UBS_STAGE_RANGES = 5,       /* ubs_bin_sort: per-tile ranges                */
+  UBS_STAGE_RASTER_FWD = 6,   /* ubs_render_fwd                               */
+  UBS_STAGE_GRAD_CLEAR = 7,   /* ubs_render_bwd: clear the record gradients   */
+  UBS_STAGE_RASTER_BWD = 8,   /* ubs_render_bwd: compositing adjoint          */
+  UBS_STAGE_PRE_BWD = 9,      /* ubs_render_bwd: per-primitive adjoint        */
+  UBS_N_STAGES = 10
+};
+
+/* A frame: the scenes, the views rendered from them, and the tuning. */
+typedef struct {
+  const ubs_scene* scenes;   /* host array [n_scenes] */
+  int32_t n_scenes;
+  int32_t n_views;
+  const ubs_view* views;     /* host array [n_views] */
+  ubs_tuning tuning;
+  void* const* stage_events; /* optional [2 * UBS_N_STAGES] hipEvent_t, or NULL */
+} ubs_frame;
+
+/*
+ * Workspace layout, filled by ubs_preprocess when ws == NULL.  Every offset
+ * is in bytes from the start of ws and 256-byte aligned.
+ *
+ *   status    ubs_status_block
+ *   records   float32 [n_records][12], AoS, record (view v, primitive i) at
+ *             index rec_base[v] + i where rec_base[v] is the sum of the
+ *             primitive counts of views 0..v-1.  Fields:
+ *               0 mean x (px)   1 mean y (px)   2 conic a   3 conic b
+ *               4 conic c       5 rho           6 o(q)      7 beta_x
+ *               8 r  9 g  10 b (colour)        11 depth (camera z)
+ *             conic = inverse of the 2-D covariance, r(p) = a dx^2 +
+ *             2 b dx dy + c dy^2 (dx = p_x - mean x); the record touches
+ *             pixels with r <= rho, where rho is the largest r with
+ *             o(q) (1 - r)^beta_x >= 1/255.  A record with !(rho > 0) is
+ *             culled.
+ *   keys      uint64 [pair_capacity] sorted keys: (global tile << 32) |
+ *             float32 bits of depth; global tile = tile_base[v] + ty *
+ *             tiles_x(v) + tx with tile_base[v] the tile count of views
+ *             0..v-1.
+ *   values    uint32 [pair_capacity] record index of each sorted key.
+ *   ranges    uint32 [n_tiles][2] [start, end) of each tile in keys;
+ *             (0, 0) for an empty tile.
+ *   ncontrib  uint32 [n_pixels] per pixel: one past the position (within
+ *             its tile's range) of its last contributor.
+ *   grad2d    float32 [n_records][10] d loss / d record fields 0-4, 6-10.
+ * Other regions are private scratch.
+ */
+typedef struct {
+  uint64_t bytes;            /* total workspace size */
+  int64_t n_records;
+  int64_t n_tiles;
+  int64_t n_pixels;          /* sum over views of width * height */
+  int64_t pair_capacity;
+  int32_t key_bits;          /* significant key bits sorted: 32 + tile bits */
+  int32_t n_views;
+  uint64_t off_status, off_records, off_keys, off_values, off_ranges;
+  uint64_t off_ncontrib, off_grad2d;
+} ubs_layout;
+
+/* Status block at ws + off_status (device memory, uint32/uint64 fields). */
+typedef struct {
+  uint64_t pairs_needed;     /* (tile, record) pairs the frame needs */
+  uint32_t overflow;         /* 1 if pairs_needed > pair_capacity */
+  uint32_t n_nonfinite;      /* primitives with non-finite parameters (culled) */
+  uint32_t n_visible;        /* records that survived culling */
+  uint32_t _pad[11];
+} ubs_status_block;
+
+/*
+ * ubs_preprocess -- per-primitive conditioning and projection.
+ * Paper: Section 4.2 (spatial-orthogonal Cholesky, Sigma = L L^T),
+ * Section 4.3 (Beta-modulated conditional slicing and opacity),
+ * Section 3 (projection J W Sigma W^T J^T, Mahalanobis distance r).
+ *
+ * ws == NULL: size query.  Validates the frame and fills *layout (which
+ * must then be non-NULL); enqueues nothing.
+ * ws != NULL: ws must hold at least layout.bytes (ws_bytes); writes the
+ * records of every (view, primitive), clears the status block and the
+ * private tables.  Culled records (behind the near plane z <= 0.2,
+ * non-positive-definite 2-D covariance, o(q) < 1/255, non-finite
+ * parameters) get rho = 0.
+ */
+ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
+                          ubs_layout* layout, void* stream);
+
+/*
+ * ubs_bin_sort -- tile binning and (tile, depth) radix sort.
+ * Reads the records in ws (written by ubs_preprocess, or by the caller in
+ * the documented record format after a ubs_preprocess call on the same
+ * frame).  A record overlaps a tile iff the minimum of r over the rectangle
+ * spanned by the tile's pixel centres (clipped to the image) is at most
+ * rho (1 + 2^-10), evaluated in float64 without contraction.  Keys are
+ * sorted ascending; equal keys keep record-index order.
+ */
+ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, void* stream);
+
+/*
+ * ubs_render_fwd -- front-to-back alpha compositing per tile.
+ * Paper: Section 3 compositing, C = sum_i c_i alpha_i prod_{j<i}(1 - alpha_j),
+ * with alpha_i = min(0.99, o(q) (1 - r)^beta_x) (Beta kernel, Section 3 and
+ * 4.3) for r <= rho; records with alpha < 1/255 are skipped, and a pixel
+ * stops before the first record that would take its transmittance below
+ * 1e-4.  Background is black: add bg * t_final yourself.
+ * image: float32 [sum_v H_v W_v][3] (views concatenated, each row-major HWC);
+ * t_final: float32 [sum_v H_v W_v] final transmittance (may be NULL).
+ */
+ubs_status ubs_render_fwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
+                          float* image, float* t_final, void* stream);
+
+/*
+ * ubs_render_bwd -- adjoint of ubs_render_fwd and ubs_preprocess.
+ * Walks each tile back to front, recovering the transmittance by division
+ * instead of storing it, reduces per-record gradients across the tile and
+ * accumulates them with atomics, then chains them through the projection,
+ * conditioning and covariance construction to every parameter.
+ * Gradient input, exactly one of:
+ *   d_image  float32 [sum_v H_v W_v][3] d loss / d image (with d_t_final
+ *            [sum_v H_v W_v] d loss / d t_final, or NULL for zero), or
+ *   l1_image and l1_target, both float32 [sum_v H_v W_v][3]: the loss is the
+ *            L1 mean |image - target| over all channels of all views, whose
+ *            image gradient sign(image - target) / (3 sum_v H_v W_v) (sign 0
+ *            at 0) is formed in-kernel; d_image and d_t_final must be NULL.
+ * Writes every scenes[s].dparams (must be non-NULL).
+ */
+ubs_status ubs_render_bwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
+                          const float* d_image, const float* d_t_final,
+                          const float* l1_image, const float* l1_target, void* stream);
+
+/* Number of parameter rows F for a scene (0 for an unsupported dim/rot). */
+int32_t ubs_param_count(int32_t dim, int32_t rot);
+
+/* ABI version (UBS_ABI_VERSION) of the loaded library. */
+int32_t ubs_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UBS_H */

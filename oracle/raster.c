@@ -263,16 +263,20 @@ int oracle_render_pixels(int n, const double *rec, const unsigned char *amb, int
  * alpha = sigma below the clamp (else constant); sigma = o (1-r)^beta gives
  *   d/do = (1-r)^beta, d/dbeta = sigma ln(1-r), d/dr = -beta sigma/(1-r),
  * and r = a dx^2 + 2 b dx dy + c dy^2 with dx = px - mx, dy = py - my.
+ * d_rec_abs (may be NULL) accumulates the absolute value of every per-pixel
+ * term instead: the scale of the rounding error of a float32 summation.
+ * Only rows [y_begin, y_end) are visited.
  */
-int oracle_render_bwd(int n, const double *rec, int W, int H, const double *d_image,
-                      const double *d_tfinal, double *d_rec)
+int oracle_render_bwd(int n, const double *rec, int W, int H, int y_begin, int y_end,
+                      const double *d_image, const double *d_tfinal, double *d_rec,
+                      double *d_rec_abs)
 {
     bands_t bd = {1e-300, 1e-300, 1e-300, 1e-300};
     rows_t R;
     build_rows(n, rec, NULL, H, &R);
     int cap = R.m > 0 ? R.m : 1;
     contrib_t *list = (contrib_t *)malloc(sizeof(contrib_t) * (size_t)cap);
-    for (int y = 0; y < H; ++y)
+    for (int y = y_begin; y < y_end; ++y)
         for (int x = 0; x < W; ++x) {
             size_t p = (size_t)y * W + x;
             double col[3], Tf;
@@ -286,9 +290,10 @@ int oracle_render_bwd(int n, const double *rec, int W, int H, const double *d_im
                 const double *r = rec + 12 * (size_t)c->id;
                 double *dr = d_rec + 10 * (size_t)c->id;
                 double a = c->alpha, Ti = c->T;
-                dr[7] += g[0] * a * Ti;
-                dr[8] += g[1] * a * Ti;
-                dr[9] += g[2] * a * Ti;
+                double t[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                t[7] = g[0] * a * Ti;
+                t[8] = g[1] * a * Ti;
+                t[9] = g[2] * a * Ti;
                 double dalpha = g[0] * Ti * (r[8] - S[0]) + g[1] * Ti * (r[9] - S[1])
                               + g[2] * Ti * (r[10] - S[2]) - gT * Tf / (1.0 - a);
                 S[0] = a * r[8] + (1.0 - a) * S[0];
@@ -296,15 +301,18 @@ int oracle_render_bwd(int n, const double *rec, int W, int H, const double *d_im
                 S[2] = a * r[10] + (1.0 - a) * S[2];
                 if (c->sigma < ALPHA_MAX) {
                     double pw = pow(c->base, r[7]);
-                    dr[5] += dalpha * pw;
-                    dr[6] += dalpha * c->sigma * log(c->base);
+                    t[5] = dalpha * pw;
+                    t[6] = dalpha * c->sigma * log(c->base);
                     double dq = dalpha * (-r[7] * c->sigma / c->base);
-                    dr[0] += dq * (-2.0) * (r[2] * c->dx + r[3] * c->dy);
-                    dr[1] += dq * (-2.0) * (r[3] * c->dx + r[4] * c->dy);
-                    dr[2] += dq * c->dx * c->dx;
-                    dr[3] += dq * 2.0 * c->dx * c->dy;
-                    dr[4] += dq * c->dy * c->dy;
+                    t[0] = dq * (-2.0) * (r[2] * c->dx + r[3] * c->dy);
+                    t[1] = dq * (-2.0) * (r[3] * c->dx + r[4] * c->dy);
+                    t[2] = dq * c->dx * c->dx;
+                    t[3] = dq * 2.0 * c->dx * c->dy;
+                    t[4] = dq * c->dy * c->dy;
                 }
+                for (int q = 0; q < 10; ++q) dr[q] += t[q];
+                if (d_rec_abs)
+                    for (int q = 0; q < 10; ++q) d_rec_abs[10 * (size_t)c->id + q] += fabs(t[q]);
             }
         }
     free(list);

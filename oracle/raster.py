@@ -38,7 +38,8 @@ def lib():
                                         ctypes.c_int, ctypes.c_int, _D, _D, _D, _I, _U]
         L.oracle_render_pixels.argtypes = [ctypes.c_int, _D, _U8, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int, _I, _I, _D, _D, _D, _I, _U]
-        L.oracle_render_bwd.argtypes = [ctypes.c_int, _D, ctypes.c_int, ctypes.c_int, _D, _D, _D]
+        L.oracle_render_bwd.argtypes = [ctypes.c_int, _D, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, _D, _D, _D, _D]
         L.oracle_bin.restype = ctypes.c_int64
         L.oracle_bin.argtypes = [ctypes.c_int, _F, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
@@ -95,16 +96,20 @@ def render_pixels(rec: np.ndarray, W: int, H: int, xs, ys, amb=None, bands=DEFAU
 
 
 def render_bwd(rec: np.ndarray, W: int, H: int, d_image: np.ndarray,
-               d_tfinal: Optional[np.ndarray] = None) -> np.ndarray:
+               d_tfinal: Optional[np.ndarray] = None, with_abs: bool = False, rows=None):
     """Adjoint of the compositing: d_rec [n,10] = (d mx, d my, d a, d b, d c,
-    d o, d beta, d r, d g, d bl)."""
+    d o, d beta, d r, d g, d bl).  With ``with_abs`` also returns the sums of
+    the absolute per-pixel terms (the scale of float32 summation error)."""
     rec = np.ascontiguousarray(rec, dtype=np.float64)
     gi = np.ascontiguousarray(d_image, dtype=np.float64)
     gt = None if d_tfinal is None else np.ascontiguousarray(d_tfinal, dtype=np.float64)
     out = np.zeros((rec.shape[0], 10))
-    lib().oracle_render_bwd(rec.shape[0], _p(rec, _D), W, H, _p(gi, _D),
-                            None if gt is None else _p(gt, _D), _p(out, _D))
-    return out
+    ab = np.zeros((rec.shape[0], 10)) if with_abs else None
+    y0, y1 = (0, H) if rows is None else rows
+    lib().oracle_render_bwd(rec.shape[0], _p(rec, _D), W, H, y0, y1, _p(gi, _D),
+                            None if gt is None else _p(gt, _D), _p(out, _D),
+                            None if ab is None else _p(ab, _D))
+    return (out, ab) if with_abs else out
 
 
 def tile_hit(mx, my, a, b, c, rho, x0, x1, y0, y1) -> bool:

@@ -60,17 +60,26 @@ def _amb_records(out: dict, amb: np.ndarray) -> np.ndarray:
 
 def render(params: np.ndarray, dim: int, rot: int, view, *, d_image: Optional[np.ndarray] = None,
            d_tfinal: Optional[np.ndarray] = None, l1_target: Optional[np.ndarray] = None,
-           rows=None, bands=raster.DEFAULT_BANDS):
+           rows=None, bands=raster.DEFAULT_BANDS, record_f32: bool = False):
     """Render one view in float64.
 
     params: [F][n] (any float dtype; promoted to float64).  If ``d_image``
     (or ``l1_target``: L1-mean loss against it, sign(0) = 0) is given, also
     returns ``dparams`` [F][n].
+
+    ``record_f32``: composite from the screen-space records rounded to
+    float32, the precision the renderer's record format fixes, instead of
+    their float64 values (the per-primitive steps and their derivatives stay
+    float64).  Parity tests against a float32-record renderer use this so
+    that rounding a record (a mean that moves by 1e-5 px next to a pixel
+    centre, say) is not counted as a difference.
     """
     want_grad = d_image is not None or l1_target is not None
     P = torch.tensor(np.asarray(params, dtype=np.float64), requires_grad=want_grad)
     out = pp.preprocess(P, dim, rot, view)
     rec = out["rec"].detach().numpy()
+    if record_f32:
+        rec = rec.astype(np.float32).astype(np.float64)
     amb = ambiguous_records(out)
     rec_f = _amb_records(out, amb) if amb.any() else rec
     W, H = view.width, view.height
@@ -82,14 +91,31 @@ def render(params: np.ndarray, dim: int, rot: int, view, *, d_image: Optional[np
         if l1_target is not None:
             d_image = np.sign(img - l1_target) / float(img.size)
             res["loss"] = float(np.abs(img - l1_target).mean())
-        d_rec = raster.render_bwd(rec, W, H, d_image, d_tfinal)
+        d_rec, d_abs = raster.render_bwd(rec, W, H, d_image, d_tfinal, with_abs=True)
         G = np.zeros_like(rec)
         G[:, _GRAD_COLS] = d_rec
-        torch.autograd.backward(out["rec"], torch.from_numpy(G))
+        torch.autograd.backward(out["rec"], torch.from_numpy(G), retain_graph=True)
         res["dparams"] = P.grad.numpy().copy()
         res["d_rec"] = d_rec
+        res["d_rec_abs"] = d_abs
         res["d_image"] = d_image
+        res["dparams_noise"] = _abs_chain(P, out["rec"], d_abs)
     return res
+
+
+def _abs_chain(P: torch.Tensor, rec: torch.Tensor, d_abs: np.ndarray) -> np.ndarray:
+    """sum_k |d rec_k / d params| * d_abs_k per parameter entry: how far a
+    float32 accumulation of the per-pixel gradient terms can move each
+    parameter gradient (records depend only on their own primitive, so one
+    vector-Jacobian product per record field gives that field's Jacobian)."""
+    acc = np.zeros(tuple(P.shape))
+    for j, col in enumerate(_GRAD_COLS):
+        if not np.any(d_abs[:, j]):
+            continue
+        (jac,) = torch.autograd.grad(rec[:, col].sum(), P, retain_graph=True, allow_unused=True)
+        if jac is not None:
+            acc += np.abs(jac.numpy()) * d_abs[None, :, j]
+    return acc
 
 
 def loss_value(params: np.ndarray, dim: int, rot: int, view, weight_image: np.ndarray,

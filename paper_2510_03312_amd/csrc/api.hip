@@ -1,0 +1,380 @@
+// extern "C" entry points of libubs: argument validation, workspace layout
+// and kernel launch sequences.  See include/ubs.h for the contract.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "ubs_internal.hpp"
+
+namespace ubs {
+
+hipError_t launch_preprocess_fwd(bool fp64, const DevScene& S, int scene, const DevView* views,
+                                 int n_views, float* records, DevStatus* status, hipStream_t st);
+hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const DevView* views,
+                                 int n_views, const float* records, const float* grad2d,
+                                 hipStream_t st);
+hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
+                            uint32_t n_records, uint32_t* counts, hipStream_t st);
+hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
+                       DevStatus* status, unsigned long long capacity, hipStream_t st);
+hipError_t launch_bin_emit(const float* records, const DevView* views, int n_views,
+                           uint32_t n_records, const uint32_t* offsets, const DevStatus* status,
+                           unsigned long long* keys, uint32_t* values, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
+hipError_t launch_ranges(const unsigned long long* keys, const DevStatus* status, uint32_t* ranges,
+                         size_t n_tiles, unsigned long long capacity, hipStream_t st);
+hipError_t launch_radix_sort(unsigned long long* k0, uint32_t* v0, unsigned long long* k1,
+                             uint32_t* v1, const DevStatus* status, int key_bits, int digit_bits,
+                             uint32_t* hist, uint32_t* tile_sums, uint32_t n_blocks,
+                             hipStream_t st);
+hipError_t launch_raster_fwd(int tw, int th, const float* records, const uint32_t* values,
+                             const uint32_t* ranges, const DevView* views, int n_views,
+                             uint32_t n_tiles, float* image, float* t_ws, float* t_user,
+                             uint32_t* ncontrib, hipStream_t st);
+hipError_t launch_raster_bwd(int tw, int th, const float* records, const uint32_t* values,
+                             const uint32_t* ranges, const DevView* views, int n_views,
+                             uint32_t n_tiles, const float* t_ws, const uint32_t* ncontrib,
+                             const float* d_image, const float* d_tfinal, const float* l1_image,
+                             const float* l1_target, float l1_scale, float* grad2d,
+                             hipStream_t st);
+
+// Descriptor upload: views are passed by value in chunks and written into
+// the workspace by a tiny kernel (no memcpy node, graph-capture safe).
+constexpr int kViewChunk = 8;
+struct ViewChunk {
+  DevView v[kViewChunk];
+  int32_t first, count;
+};
+
+__global__ void upload_views_kernel(ViewChunk c, DevView* __restrict__ dst) {
+  const int k = threadIdx.x;
+  if (k < c.count) dst[c.first + k] = c.v[k];
+}
+
+__global__ void reset_status_kernel(DevStatus* __restrict__ s) {
+  if (threadIdx.x == 0) {
+    s->pairs_needed = 0;
+    s->overflow = 0;
+    s->n_nonfinite = 0;
+    s->n_visible = 0;
+    s->work_counter[0] = s->work_counter[1] = s->work_counter[2] = 0;
+  }
+}
+
+__global__ void fill_f32_kernel(float* __restrict__ p, size_t n) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t k = i; k < n; k += stride) p[k] = 0.0f;
+}
+
+static void stage_mark(const ubs_frame* f, int stage, int end, hipStream_t s) {
+  if (f->stage_events) {
+    hipEvent_t e = static_cast<hipEvent_t>(f->stage_events[2 * stage + end]);
+    if (e) (void)hipEventRecord(e, s);
+  }
+}
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+static bool finite_f(float x) { return isfinite(x) != 0; }
+
+static bool tile_ok(int tw, int th) {
+  return (tw == 16 && th == 16) || (tw == 16 && th == 8) || (tw == 8 && th == 8) ||
+         (tw == 32 && th == 16);
+}
+
+// Validates the frame and computes the layout and the device descriptors.
+static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
+                       std::vector<DevScene>* ds) {
+  if (!f) return UBS_ERR_ARG;
+  if (f->n_scenes < 0 || f->n_scenes > UBS_MAX_SCENES) return UBS_ERR_ARG;
+  if (f->n_views < 0 || f->n_views > UBS_MAX_VIEWS) return UBS_ERR_ARG;
+  if (f->n_scenes > 0 && !f->scenes) return UBS_ERR_ARG;
+  if (f->n_views > 0 && !f->views) return UBS_ERR_ARG;
+  const ubs_tuning& tu = f->tuning;
+  if (!tile_ok(tu.tile_w, tu.tile_h)) return UBS_ERR_UNSUPPORTED;
+  if (tu.digit_bits < 4 || tu.digit_bits > 8) return UBS_ERR_UNSUPPORTED;
+  if (tu.pair_capacity < 0 || tu.pair_capacity > int64_t(0x7fffffff)) return UBS_ERR_ARG;
+  ds->clear();
+  dv->clear();
+  for (int s = 0; s < f->n_scenes; ++s) {
+    const ubs_scene& S = f->scenes[s];
+    if (S.dim < 3 || S.dim > 7) return UBS_ERR_ARG;
+    if (S.dim == 4 || S.dim == 5) return UBS_ERR_UNSUPPORTED;
+    if (S.rot != UBS_ROT_QUAT && S.rot != UBS_ROT_SKEW) return UBS_ERR_ARG;
+    if (S.n < 0 || S.n > int64_t(0x7fffffff)) return UBS_ERR_ARG;
+    if (S.n > 0 && !S.params) return UBS_ERR_ARG;
+    DevScene d{};
+    d.params = S.params;
+    d.dparams = S.dparams;
+    d.n = S.n;
+    d.dim = S.dim;
+    d.rot = S.rot;
+    d.F = param_rows(S.dim - 3, S.rot).F;
+    ds->push_back(d);
+  }
+  uint64_t n_rec = 0, n_tiles = 0, n_pix = 0;
+  for (int v = 0; v < f->n_views; ++v) {
+    const ubs_view& V = f->views[v];
+    if (V.scene < 0 || V.scene >= f->n_scenes) return UBS_ERR_ARG;
+    if (V.width < 1 || V.height < 1 || V.width > 16384 || V.height > 16384) return UBS_ERR_ARG;
+    for (int k = 0; k < 9; ++k) if (!finite_f(V.R[k])) return UBS_ERR_ARG;
+    for (int k = 0; k < 3; ++k) if (!finite_f(V.t[k])) return UBS_ERR_ARG;
+    if (!(V.fx > 0.0f) || !(V.fy > 0.0f) || !finite_f(V.fx) || !finite_f(V.fy) ||
+        !finite_f(V.cx) || !finite_f(V.cy) || !finite_f(V.time))
+      return UBS_ERR_ARG;
+    DevView d{};
+    memcpy(d.R, V.R, sizeof(d.R));
+    memcpy(d.t, V.t, sizeof(d.t));
+    for (int k = 0; k < 3; ++k)  // camera centre -R^T t
+      d.cam[k] = -(double(V.R[k]) * V.t[0] + double(V.R[3 + k]) * V.t[1] + double(V.R[6 + k]) * V.t[2]);
+    d.fx = V.fx; d.fy = V.fy; d.cx = V.cx; d.cy = V.cy; d.time = V.time;
+    d.scene = V.scene;
+    d.W = V.width; d.H = V.height;
+    d.tile_w = tu.tile_w; d.tile_h = tu.tile_h;
+    d.tiles_x = (V.width + tu.tile_w - 1) / tu.tile_w;
+    d.tiles_y = (V.height + tu.tile_h - 1) / tu.tile_h;
+    d.tile_base = uint32_t(n_tiles);
+    d.rec_base = uint32_t(n_rec);
+    d.pix_base = uint32_t(n_pix);
+    n_rec += uint64_t(f->scenes[V.scene].n);
+    n_tiles += uint64_t(d.tiles_x) * uint64_t(d.tiles_y);
+    n_pix += uint64_t(V.width) * uint64_t(V.height);
+    if (n_rec > 0x7fffffffull || n_tiles > 0x7fffffffull || n_pix > 0x7fffffffull)
+      return UBS_ERR_UNSUPPORTED;
+    dv->push_back(d);
+  }
+  Layout& l = *L;
+  memset(&l, 0, sizeof(l));
+  l.pub.n_records = int64_t(n_rec);
+  l.pub.n_tiles = int64_t(n_tiles);
+  l.pub.n_pixels = int64_t(n_pix);
+  l.pub.pair_capacity = tu.pair_capacity;
+  l.pub.n_views = f->n_views;
+  l.tile_w = tu.tile_w;
+  l.tile_h = tu.tile_h;
+  l.digit_bits = tu.digit_bits;
+  const int tile_bits = n_tiles > 1 ? ceil_log2_u64(n_tiles) : 0;
+  l.pub.key_bits = 32 + tile_bits;
+  l.n_passes = (l.pub.key_bits + tu.digit_bits - 1) / tu.digit_bits;
+  const uint64_t cap = uint64_t(tu.pair_capacity);
+  l.n_sort_blocks = int64_t((cap + kSortTile - 1) / kSortTile);
+  const uint64_t rec_scan_tiles = (n_rec + kScanTile - 1) / kScanTile;
+  const uint64_t hist_entries = uint64_t(1u << tu.digit_bits) * uint64_t(l.n_sort_blocks);
+  const uint64_t hist_scan_tiles = (hist_entries + kScanTile - 1) / kScanTile;
+  l.n_scan_blocks = int64_t(rec_scan_tiles > hist_scan_tiles ? rec_scan_tiles : hist_scan_tiles);
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) { const uint64_t o = off; off = align256(off + bytes); return o; };
+  l.pub.off_status = take(sizeof(DevStatus));
+  l.off_views = take(sizeof(DevView) * uint64_t(f->n_views > 0 ? f->n_views : 1));
+  l.off_scenes = take(sizeof(DevScene) * uint64_t(f->n_scenes > 0 ? f->n_scenes : 1));
+  l.pub.off_records = take(uint64_t(kRecFloats) * 4 * n_rec);
+  l.off_counts = take(4 * n_rec);
+  l.off_offsets = take(4 * n_rec);
+  l.off_blocksums = take(4 * uint64_t(l.n_scan_blocks + 1));
+  l.off_keys0 = take(8 * cap);
+  l.off_keys_alt = take(8 * cap);
+  l.off_values0 = take(4 * cap);
+  l.off_values_alt = take(4 * cap);
+  l.off_hist = take(4 * hist_entries);
+  l.pub.off_ranges = take(8 * n_tiles);
+  l.pub.off_ncontrib = take(4 * n_pix);
+  l.pub.off_grad2d = take(uint64_t(kGradFloats) * 4 * n_rec);
+  l.off_tfinal_ws = take(4 * n_pix);
+  l.pub.bytes = off;
+  const bool odd = (l.n_passes & 1) != 0;
+  l.pub.off_keys = odd ? l.off_keys_alt : l.off_keys0;
+  l.pub.off_values = odd ? l.off_values_alt : l.off_values0;
+  return UBS_OK;
+}
+
+template <typename P>
+static P* at(void* ws, uint64_t off) {
+  return reinterpret_cast<P*>(static_cast<char*>(ws) + off);
+}
+
+#define UBS_HIP(call)                         \
+  do {                                        \
+    if ((call) != hipSuccess) return UBS_ERR_HIP; \
+  } while (0)
+
+struct Plan {
+  Layout L;
+  std::vector<DevView> dv;
+  std::vector<DevScene> ds;
+};
+
+static ubs_status prepare(const ubs_frame* f, void* ws, uint64_t ws_bytes, Plan* p) {
+  const ubs_status st = plan(f, &p->L, &p->dv, &p->ds);
+  if (st != UBS_OK) return st;
+  if (!ws) return UBS_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return UBS_ERR_ARG;
+  if (ws_bytes < p->L.pub.bytes) return UBS_ERR_CAPACITY;
+  return UBS_OK;
+}
+
+}  // namespace ubs
+
+using namespace ubs;
+
+extern "C" {
+
+int32_t ubs_abi_version(void) { return UBS_ABI_VERSION; }
+
+int32_t ubs_param_count(int32_t dim, int32_t rot) {
+  if (dim != 3 && dim != 6 && dim != 7) return 0;
+  if (rot != UBS_ROT_QUAT && rot != UBS_ROT_SKEW) return 0;
+  return param_rows(dim - 3, rot).F;
+}
+
+ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes, ubs_layout* layout,
+                          void* stream) {
+  Plan p;
+  if (!ws) {
+    const ubs_status st = plan(frame, &p.L, &p.dv, &p.ds);
+    if (st != UBS_OK) return st;
+    if (!layout) return UBS_ERR_ARG;
+    *layout = p.L.pub;
+    return UBS_OK;
+  }
+  const ubs_status st = prepare(frame, ws, ws_bytes, &p);
+  if (st != UBS_OK) return st;
+  if (layout) *layout = p.L.pub;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Layout& L = p.L;
+  DevStatus* status = at<DevStatus>(ws, L.pub.off_status);
+  DevView* views = at<DevView>(ws, L.off_views);
+  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, status);
+  for (int first = 0; first < frame->n_views; first += kViewChunk) {
+    ViewChunk c{};
+    c.first = first;
+    c.count = frame->n_views - first < kViewChunk ? frame->n_views - first : kViewChunk;
+    for (int k = 0; k < c.count; ++k) c.v[k] = p.dv[first + k];
+    hipLaunchKernelGGL(upload_views_kernel, dim3(1), dim3(64), 0, s, c, views);
+  }
+  UBS_HIP(hipGetLastError());
+  const bool fp64 = (frame->tuning.flags & UBS_TUNE_PRE_FP32) == 0;
+  float* records = at<float>(ws, L.pub.off_records);
+  stage_mark(frame, UBS_STAGE_PREPROCESS, 0, s);
+  for (int sc = 0; sc < frame->n_scenes; ++sc) {
+    bool used = false;
+    for (const DevView& v : p.dv) used = used || v.scene == sc;
+    if (!used) continue;
+    UBS_HIP(launch_preprocess_fwd(fp64, p.ds[sc], sc, views, frame->n_views, records, status, s));
+  }
+  stage_mark(frame, UBS_STAGE_PREPROCESS, 1, s);
+  return UBS_OK;
+}
+
+ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, void* stream) {
+  Plan p;
+  const ubs_status st = prepare(frame, ws, ws_bytes, &p);
+  if (st != UBS_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Layout& L = p.L;
+  DevStatus* status = at<DevStatus>(ws, L.pub.off_status);
+  const DevView* views = at<DevView>(ws, L.off_views);
+  const float* records = at<float>(ws, L.pub.off_records);
+  uint32_t* counts = at<uint32_t>(ws, L.off_counts);
+  uint32_t* offsets = at<uint32_t>(ws, L.off_offsets);
+  uint32_t* sums = at<uint32_t>(ws, L.off_blocksums);
+  const uint32_t n_rec = uint32_t(L.pub.n_records);
+  const unsigned long long cap = (unsigned long long)L.pub.pair_capacity;
+  auto* k0 = at<unsigned long long>(ws, L.off_keys0);
+  auto* k1 = at<unsigned long long>(ws, L.off_keys_alt);
+  auto* v0 = at<uint32_t>(ws, L.off_values0);
+  auto* v1 = at<uint32_t>(ws, L.off_values_alt);
+  stage_mark(frame, UBS_STAGE_BIN_COUNT, 0, s);
+  UBS_HIP(launch_bin_count(records, views, frame->n_views, n_rec, counts, s));
+  stage_mark(frame, UBS_STAGE_BIN_COUNT, 1, s);
+  stage_mark(frame, UBS_STAGE_SCAN, 0, s);
+  UBS_HIP(launch_scan(counts, n_rec, sums, offsets, status, cap, s));
+  stage_mark(frame, UBS_STAGE_SCAN, 1, s);
+  stage_mark(frame, UBS_STAGE_BIN_EMIT, 0, s);
+  UBS_HIP(launch_bin_emit(records, views, frame->n_views, n_rec, offsets, status, k0, v0, s));
+  stage_mark(frame, UBS_STAGE_BIN_EMIT, 1, s);
+  stage_mark(frame, UBS_STAGE_SORT, 0, s);
+  UBS_HIP(launch_radix_sort(k0, v0, k1, v1, status, L.pub.key_bits, L.digit_bits,
+                            at<uint32_t>(ws, L.off_hist), sums, uint32_t(L.n_sort_blocks), s));
+  stage_mark(frame, UBS_STAGE_SORT, 1, s);
+  stage_mark(frame, UBS_STAGE_RANGES, 0, s);
+  UBS_HIP(launch_ranges(at<unsigned long long>(ws, L.pub.off_keys), status,
+                        at<uint32_t>(ws, L.pub.off_ranges), size_t(L.pub.n_tiles), cap, s));
+  stage_mark(frame, UBS_STAGE_RANGES, 1, s);
+  return UBS_OK;
+}
+
+ubs_status ubs_render_fwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes, float* image,
+                          float* t_final, void* stream) {
+  Plan p;
+  const ubs_status st = prepare(frame, ws, ws_bytes, &p);
+  if (st != UBS_OK) return st;
+  if (!image && p.L.pub.n_pixels > 0) return UBS_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Layout& L = p.L;
+  stage_mark(frame, UBS_STAGE_RASTER_FWD, 0, s);
+  UBS_HIP(launch_raster_fwd(L.tile_w, L.tile_h, at<float>(ws, L.pub.off_records),
+                            at<uint32_t>(ws, L.pub.off_values), at<uint32_t>(ws, L.pub.off_ranges),
+                            at<DevView>(ws, L.off_views), frame->n_views, uint32_t(L.pub.n_tiles),
+                            image, at<float>(ws, L.off_tfinal_ws), t_final,
+                            at<uint32_t>(ws, L.pub.off_ncontrib), s));
+  stage_mark(frame, UBS_STAGE_RASTER_FWD, 1, s);
+  return UBS_OK;
+}
+
+ubs_status ubs_render_bwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
+                          const float* d_image, const float* d_t_final, const float* l1_image,
+                          const float* l1_target, void* stream) {
+  Plan p;
+  const ubs_status st = prepare(frame, ws, ws_bytes, &p);
+  if (st != UBS_OK) return st;
+  const bool has_d = d_image != nullptr;
+  const bool has_l1 = l1_image != nullptr || l1_target != nullptr;
+  if (has_d == has_l1) return UBS_ERR_ARG;
+  if (has_l1 && (!l1_image || !l1_target || d_t_final)) return UBS_ERR_ARG;
+  for (int sc = 0; sc < frame->n_scenes; ++sc)
+    if (frame->scenes[sc].n > 0 && !frame->scenes[sc].dparams) return UBS_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Layout& L = p.L;
+  float* grad2d = at<float>(ws, L.pub.off_grad2d);
+  const size_t ng = size_t(L.pub.n_records) * kGradFloats;
+  stage_mark(frame, UBS_STAGE_GRAD_CLEAR, 0, s);
+  if (ng > 0) {
+    size_t blocks = (ng + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, grad2d, ng);
+  }
+  stage_mark(frame, UBS_STAGE_GRAD_CLEAR, 1, s);
+  const float l1_scale = L.pub.n_pixels > 0 ? float(1.0 / (3.0 * double(L.pub.n_pixels))) : 0.0f;
+  const DevView* views = at<DevView>(ws, L.off_views);
+  stage_mark(frame, UBS_STAGE_RASTER_BWD, 0, s);
+  UBS_HIP(launch_raster_bwd(L.tile_w, L.tile_h, at<float>(ws, L.pub.off_records),
+                            at<uint32_t>(ws, L.pub.off_values), at<uint32_t>(ws, L.pub.off_ranges),
+                            views, frame->n_views, uint32_t(L.pub.n_tiles),
+                            at<float>(ws, L.off_tfinal_ws), at<uint32_t>(ws, L.pub.off_ncontrib),
+                            d_image, d_t_final, l1_image, l1_target, l1_scale, grad2d, s));
+  stage_mark(frame, UBS_STAGE_RASTER_BWD, 1, s);
+  const bool fp64 = (frame->tuning.flags & UBS_TUNE_PRE_FP32) == 0;
+  stage_mark(frame, UBS_STAGE_PRE_BWD, 0, s);
+  for (int sc = 0; sc < frame->n_scenes; ++sc) {
+    if (p.ds[sc].n == 0) continue;
+    bool used = false;
+    for (const DevView& v : p.dv) used = used || v.scene == sc;
+    if (!used) {  // a scene no view sees has zero gradient
+      const size_t nf = size_t(p.ds[sc].F) * size_t(p.ds[sc].n);
+      size_t blocks = (nf + 255) / 256;
+      if (blocks > 8192) blocks = 8192;
+      hipLaunchKernelGGL(fill_f32_kernel, dim3(unsigned(blocks)), dim3(256), 0, s,
+                         p.ds[sc].dparams, nf);
+      continue;
+    }
+    UBS_HIP(launch_preprocess_bwd(fp64, p.ds[sc], sc, views, frame->n_views,
+                                  at<float>(ws, L.pub.off_records), grad2d, s));
+  }
+  stage_mark(frame, UBS_STAGE_PRE_BWD, 1, s);
+  UBS_HIP(hipGetLastError());
+  return UBS_OK;
+}
+
+}  // extern "C"

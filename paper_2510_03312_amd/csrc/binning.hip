@@ -1,0 +1,296 @@
+// Tile binning: per-record tile counts, exclusive scan, key/value emission,
+// per-tile ranges.
+//
+// A record overlaps a tile iff the minimum of its quadratic form
+// r(p) = a dx^2 + 2 b dx dy + c dy^2 over the rectangle spanned by the
+// tile's pixel centres (clipped to the image) is at most rho (1 + 2^-10).
+// The test is evaluated in float64, round-to-nearest, with no contraction
+// and in a fixed operation order, so that the decision is reproducible
+// bit for bit by any IEEE-754 implementation of the same expression.
+#include "ubs_internal.hpp"
+
+namespace ubs {
+
+#pragma clang fp contract(off)
+__device__ __noinline__ bool tile_overlap_exact(double mx, double my, double a, double b, double c,
+                                                double rho, double x0, double x1, double y0,
+                                                double y1) {
+  const double rb = rho * (1.0 + 0x1p-10);
+  if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return true;
+  const double det = a * c - b * b;
+  const double dy0 = y0 - my, dy1 = y1 - my;
+  const double dx0 = x0 - mx, dx1 = x1 - mx;
+  // vertical edges: dx fixed, minimiser dy* = -b dx / c clamped to [dy0, dy1]
+  for (int e = 0; e < 2; ++e) {
+    const double dx = e == 0 ? dx0 : dx1;
+    const double t = -(b * dx);
+    const double lo = c * dy0, hi = c * dy1;
+    if (t >= lo && t <= hi) {
+      if ((det * dx) * dx <= rb * c) return true;
+    } else {
+      const double dy = (t < lo) ? dy0 : dy1;
+      const double q = ((a * dx) * dx + ((2.0 * b) * dx) * dy) + (c * dy) * dy;
+      if (q <= rb) return true;
+    }
+  }
+  // horizontal edges: dy fixed, minimiser dx* = -b dy / a clamped to [dx0, dx1]
+  for (int e = 0; e < 2; ++e) {
+    const double dy = e == 0 ? dy0 : dy1;
+    const double t = -(b * dy);
+    const double lo = a * dx0, hi = a * dx1;
+    if (t >= lo && t <= hi) {
+      if ((det * dy) * dy <= rb * a) return true;
+    } else {
+      const double dx = (t < lo) ? dx0 : dx1;
+      const double q = ((a * dx) * dx + ((2.0 * b) * dx) * dy) + (c * dy) * dy;
+      if (q <= rb) return true;
+    }
+  }
+  return false;
+}
+#pragma clang fp contract(on)
+
+// View of a record: views are laid out with ascending rec_base.
+__device__ __forceinline__ int view_of_record(const DevView* __restrict__ views, int n_views,
+                                              uint32_t rec) {
+  int lo = 0, hi = n_views - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (views[mid].rec_base <= rec) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct TileBox {
+  int tx0, tx1, ty0, ty1;  // inclusive; empty if tx0 > tx1
+};
+
+// Conservative tile bounding box of {r <= rho (1 + 2^-10)}, padded by 2 px.
+__device__ __forceinline__ TileBox record_tile_box(const float4 r0, const float4 r1,
+                                                   const DevView& V) {
+  TileBox bx{1, 0, 1, 0};
+  const float mx = r0.x, my = r0.y, a = r0.z, b = r0.w, c = r1.x, rho = r1.y;
+  if (!(rho > 0.0f)) return bx;
+  const float det = a * c - b * b;
+  if (!(det > 0.0f) || !(a > 0.0f) || !(c > 0.0f)) return bx;
+  const float rb = rho * (1.0f + 0x1p-9f);
+  const float ex = sqrtf(rb * c / det), ey = sqrtf(rb * a / det);
+  const float xl = mx - ex - 2.0f, xh = mx + ex + 2.0f;
+  const float yl = my - ey - 2.0f, yh = my + ey + 2.0f;
+  if (!(xh >= 0.0f) || !(yh >= 0.0f) || !(xl <= float(V.W)) || !(yl <= float(V.H))) return bx;
+  bx.tx0 = int(floorf(fmaxf(xl, 0.0f) / float(V.tile_w)));
+  bx.tx1 = min(V.tiles_x - 1, int(floorf(fminf(xh, float(V.W)) / float(V.tile_w))));
+  bx.ty0 = int(floorf(fmaxf(yl, 0.0f) / float(V.tile_h)));
+  bx.ty1 = min(V.tiles_y - 1, int(floorf(fminf(yh, float(V.H)) / float(V.tile_h))));
+  return bx;
+}
+
+__device__ __forceinline__ bool record_hits_tile(const float4 r0, const float4 r1, const DevView& V,
+                                                 int tx, int ty) {
+  const int px0 = tx * V.tile_w, py0 = ty * V.tile_h;
+  const int px1 = min(px0 + V.tile_w - 1, V.W - 1), py1 = min(py0 + V.tile_h - 1, V.H - 1);
+  return tile_overlap_exact(double(r0.x), double(r0.y), double(r0.z), double(r0.w), double(r1.x),
+                            double(r1.y), double(px0) + 0.5, double(px1) + 0.5, double(py0) + 0.5,
+                            double(py1) + 0.5);
+}
+
+__global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict__ records,
+                                                        const DevView* __restrict__ views,
+                                                        int n_views, uint32_t n_records,
+                                                        uint32_t* __restrict__ counts) {
+  const uint32_t rec = blockIdx.x * 256u + threadIdx.x;
+  if (rec >= n_records) return;
+  const float4* rp = reinterpret_cast<const float4*>(records + size_t(rec) * kRecFloats);
+  const float4 r0 = rp[0], r1 = rp[1];
+  const DevView& V = views[view_of_record(views, n_views, rec)];
+  const TileBox bx = record_tile_box(r0, r1, V);
+  uint32_t cnt = 0;
+  for (int ty = bx.ty0; ty <= bx.ty1; ++ty)
+    for (int tx = bx.tx0; tx <= bx.tx1; ++tx) cnt += record_hits_tile(r0, r1, V, tx, ty) ? 1u : 0u;
+  counts[rec] = cnt;
+}
+
+__global__ void __launch_bounds__(256) bin_emit_kernel(const float* __restrict__ records,
+                                                       const DevView* __restrict__ views,
+                                                       int n_views, uint32_t n_records,
+                                                       const uint32_t* __restrict__ offsets,
+                                                       const DevStatus* __restrict__ status,
+                                                       unsigned long long* __restrict__ keys,
+                                                       uint32_t* __restrict__ values) {
+  const uint32_t rec = blockIdx.x * 256u + threadIdx.x;
+  if (rec >= n_records) return;
+  if (status->overflow) return;
+  const float4* rp = reinterpret_cast<const float4*>(records + size_t(rec) * kRecFloats);
+  const float4 r0 = rp[0], r1 = rp[1];
+  const float depth = records[size_t(rec) * kRecFloats + 11];
+  const DevView& V = views[view_of_record(views, n_views, rec)];
+  const TileBox bx = record_tile_box(r0, r1, V);
+  uint32_t pos = offsets[rec];
+  const unsigned long long dbits = __float_as_uint(depth);
+  for (int ty = bx.ty0; ty <= bx.ty1; ++ty)
+    for (int tx = bx.tx0; tx <= bx.tx1; ++tx) {
+      if (record_hits_tile(r0, r1, V, tx, ty)) {
+        const unsigned long long tile =
+            (unsigned long long)V.tile_base + (unsigned long long)(ty * V.tiles_x + tx);
+        keys[pos] = (tile << 32) | dbits;
+        values[pos] = rec;
+        ++pos;
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of uint32 counts (three phases: tile sums, scan of the tile
+// sums in one block, tile-local scan plus the tile's base).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t block_exclusive_scan_u32(uint32_t v, uint32_t* lds,
+                                                             uint32_t* total) {
+  // 256 threads = 4 waves of 64
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[wave] = x;
+  __syncthreads();
+  uint32_t wbase = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    uint32_t s = lds[w];
+    if (w < wave) wbase += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return wbase + x - v;
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_tile_sums_kernel(
+    const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ tile_sums) {
+  __shared__ uint32_t lds[8];
+  const size_t base = size_t(blockIdx.x) * kScanTile + size_t(threadIdx.x) * kScanItems;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) s += in[base + k];
+  uint32_t tot;
+  block_exclusive_scan_u32(s, lds, &tot);
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+// One block scans all tile sums in place (exclusive) and writes the total.
+__global__ void __launch_bounds__(kScanThreads) scan_tile_sums_scan_kernel(
+    uint32_t* __restrict__ tile_sums, uint32_t n_tiles, DevStatus* __restrict__ status,
+    unsigned long long capacity) {
+  __shared__ uint32_t lds[8];
+  unsigned long long carry = 0;
+  for (uint32_t base = 0; base < n_tiles; base += kScanThreads) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t v = i < n_tiles ? tile_sums[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan_u32(v, lds, &tot);
+    if (i < n_tiles) tile_sums[i] = uint32_t(carry + ex);
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && status != nullptr) {
+    status->pairs_needed = carry;
+    status->overflow = carry > capacity ? 1u : 0u;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(
+    const uint32_t* __restrict__ in, uint32_t n, const uint32_t* __restrict__ tile_sums,
+    uint32_t* __restrict__ out) {
+  __shared__ uint32_t lds[8];
+  const size_t base = size_t(blockIdx.x) * kScanTile + size_t(threadIdx.x) * kScanItems;
+  uint32_t vals[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    vals[k] = base + k < n ? in[base + k] : 0u;
+    s += vals[k];
+  }
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan_u32(s, lds, &tot) + tile_sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += vals[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-tile ranges over the sorted keys.
+// ---------------------------------------------------------------------------
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, size_t n, uint32_t v) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t k = i; k < n; k += stride) p[k] = v;
+}
+
+__global__ void __launch_bounds__(256) ranges_kernel(const unsigned long long* __restrict__ keys,
+                                                     const DevStatus* __restrict__ status,
+                                                     uint32_t* __restrict__ ranges) {
+  const unsigned long long K = status->overflow ? 0ull : status->pairs_needed;
+  const size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= K) return;
+  const uint32_t tile = uint32_t(keys[i] >> 32);
+  if (i == 0 || uint32_t(keys[i - 1] >> 32) != tile) ranges[2 * size_t(tile)] = uint32_t(i);
+  if (i + 1 == K || uint32_t(keys[i + 1] >> 32) != tile) ranges[2 * size_t(tile) + 1] = uint32_t(i + 1);
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
+                            uint32_t n_records, uint32_t* counts, hipStream_t st) {
+  if (n_records == 0) return hipSuccess;
+  hipLaunchKernelGGL(bin_count_kernel, dim3((n_records + 255) / 256), dim3(256), 0, st, records,
+                     views, n_views, n_records, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
+                       DevStatus* status, unsigned long long capacity, hipStream_t st) {
+  const uint32_t n_tiles = (n + kScanTile - 1) / kScanTile;
+  if (n_tiles > 0)
+    hipLaunchKernelGGL(scan_tile_sums_kernel, dim3(n_tiles), dim3(kScanThreads), 0, st, in, n,
+                       tile_sums);
+  hipLaunchKernelGGL(scan_tile_sums_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, tile_sums,
+                     n_tiles, status, capacity);
+  if (n_tiles > 0)
+    hipLaunchKernelGGL(scan_apply_kernel, dim3(n_tiles), dim3(kScanThreads), 0, st, in, n,
+                       tile_sums, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_emit(const float* records, const DevView* views, int n_views,
+                           uint32_t n_records, const uint32_t* offsets, const DevStatus* status,
+                           unsigned long long* keys, uint32_t* values, hipStream_t st) {
+  if (n_records == 0) return hipSuccess;
+  hipLaunchKernelGGL(bin_emit_kernel, dim3((n_records + 255) / 256), dim3(256), 0, st, records,
+                     views, n_views, n_records, offsets, status, keys, values);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_ranges(const unsigned long long* keys, const DevStatus* status, uint32_t* ranges,
+                         size_t n_tiles, unsigned long long capacity, hipStream_t st) {
+  hipError_t e = launch_fill_u32(ranges, 2 * n_tiles, 0u, st);
+  if (e != hipSuccess) return e;
+  if (capacity == 0) return hipSuccess;
+  hipLaunchKernelGGL(ranges_kernel, dim3(unsigned((capacity + 255) / 256)), dim3(256), 0, st, keys,
+                     status, ranges);
+  return hipGetLastError();
+}
+
+}  // namespace ubs

@@ -1,0 +1,170 @@
+// Per-primitive kernels: forward preprocess (parameters -> screen-space
+// records for every view of the primitive's scene) and its adjoint
+// (gradients of the records, summed over views -> gradients of every
+// parameter).  One lane per primitive; a lane reads its parameters once
+// (component-major rows, so a wavefront's loads of one row are contiguous)
+// and loops over the views of its scene.
+#include "prim_math.hpp"
+
+namespace ubs {
+
+template <typename T, int C, int ROT>
+__global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int scene,
+                                                             const DevView* __restrict__ views,
+                                                             int n_views, float* __restrict__ records,
+                                                             DevStatus* __restrict__ status) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const bool active = i < S.n;
+  bool finite = true;
+  Raw<C, ROT> r;
+  Geo<T, C, ROT> g;
+  if (active) {
+    load_raw<C, ROT>(S.params, S.n, i, r);
+    finite = r.finite;
+    geo_forward<T, C, ROT>(r, g);
+  }
+  uint32_t visible = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const DevView& V = views[v];
+    if (V.scene != scene) continue;
+    if (!active) continue;
+    ViewState<T, C> s;
+    view_forward<T, C, ROT>(r, g, V, s);
+    bool live = s.live && finite;
+    float4 o0, o1, o2;
+    if (live) {
+      o0 = make_float4(float(s.mx), float(s.my), float(s.ca), float(s.cb));
+      o1 = make_float4(float(s.cc), float(s.rho), float(s.oq), float(s.beta));
+      o2 = make_float4(r.rgb[0], r.rgb[1], r.rgb[2], float(s.p[2]));
+      if (!isfinite(o0.x) || !isfinite(o0.y) || !isfinite(o0.z) || !isfinite(o0.w) ||
+          !isfinite(o1.x) || !isfinite(o1.y) || !isfinite(o1.z) || !isfinite(o1.w) ||
+          !(o1.y > 0.0f)) {
+        live = false;
+      }
+    }
+    if (!live) {
+      o0 = make_float4(0.f, 0.f, 0.f, 0.f);
+      o1 = make_float4(0.f, 0.f, 0.f, 0.f);
+      o2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      ++visible;
+    }
+    const size_t rec = size_t(V.rec_base) + size_t(i);
+    float4* rp = reinterpret_cast<float4*>(records + rec * kRecFloats);
+    rp[0] = o0;
+    rp[1] = o1;
+    rp[2] = o2;
+  }
+  // wavefront-aggregated counters
+  const unsigned long long nf = __ballot(active && !finite);
+  const int lane = threadIdx.x & 63;
+  uint32_t vis = visible;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) vis += __shfl_xor(vis, o, 64);
+  if (lane == 0) {
+    if (nf) atomicAdd(&status->n_nonfinite, uint32_t(__popcll(nf)));
+    if (vis) atomicAdd(&status->n_visible, vis);
+  }
+}
+
+template <typename T, int C, int ROT>
+__global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int scene,
+                                                             const DevView* __restrict__ views,
+                                                             int n_views,
+                                                             const float* __restrict__ records,
+                                                             const float* __restrict__ grad2d) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= S.n) return;
+  Raw<C, ROT> r;
+  load_raw<C, ROT>(S.params, S.n, i, r);
+  Geo<T, C, ROT> g;
+  geo_forward<T, C, ROT>(r, g);
+  GeoGrad<T, C> G;
+  geograd_zero<T, C>(G);
+  for (int v = 0; v < n_views; ++v) {
+    const DevView& V = views[v];
+    if (V.scene != scene) continue;
+    const size_t rec = size_t(V.rec_base) + size_t(i);
+    // the forward wrote rho > 0 exactly for the records it kept
+    if (!(records[rec * kRecFloats + 5] > 0.0f)) continue;
+    float gr[kGradFloats];
+    const float* gp = grad2d + rec * kGradFloats;
+#pragma unroll
+    for (int k = 0; k < kGradFloats; ++k) gr[k] = gp[k];
+    ViewState<T, C> s;
+    view_forward<T, C, ROT>(r, g, V, s);
+    view_backward<T, C, ROT>(r, g, V, s, gr, G);
+  }
+  const ParamRows pr = param_rows(C, ROT);
+  float out[64];
+  geo_backward<T, C, ROT>(r, g, G, out);
+#pragma unroll
+  for (int k = 0; k < pr.F; ++k) S.dparams[int64_t(k) * S.n + i] = out[k];
+}
+
+template <typename T, int C, int ROT>
+static hipError_t pre_fwd_t(const DevScene& S, int scene, const DevView* views, int n_views,
+                            float* records, DevStatus* status, hipStream_t st) {
+  const unsigned blocks = unsigned((S.n + 255) / 256);
+  hipLaunchKernelGGL((preprocess_fwd_kernel<T, C, ROT>), dim3(blocks), dim3(256), 0, st, S, scene,
+                     views, n_views, records, status);
+  return hipGetLastError();
+}
+
+template <typename T, int C, int ROT>
+static hipError_t pre_bwd_t(const DevScene& S, int scene, const DevView* views, int n_views,
+                            const float* records, const float* grad2d, hipStream_t st) {
+  const unsigned blocks = unsigned((S.n + 255) / 256);
+  hipLaunchKernelGGL((preprocess_bwd_kernel<T, C, ROT>), dim3(blocks), dim3(256), 0, st, S, scene,
+                     views, n_views, records, grad2d);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t pre_fwd_dispatch(const DevScene& S, int scene, const DevView* views, int n_views,
+                                   float* records, DevStatus* status, hipStream_t st) {
+  const int C = S.dim - 3;
+  if (S.rot == UBS_ROT_QUAT) {
+    if (C == 0) return pre_fwd_t<T, 0, 0>(S, scene, views, n_views, records, status, st);
+    if (C == 3) return pre_fwd_t<T, 3, 0>(S, scene, views, n_views, records, status, st);
+    if (C == 4) return pre_fwd_t<T, 4, 0>(S, scene, views, n_views, records, status, st);
+  } else {
+    if (C == 0) return pre_fwd_t<T, 0, 1>(S, scene, views, n_views, records, status, st);
+    if (C == 3) return pre_fwd_t<T, 3, 1>(S, scene, views, n_views, records, status, st);
+    if (C == 4) return pre_fwd_t<T, 4, 1>(S, scene, views, n_views, records, status, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t pre_bwd_dispatch(const DevScene& S, int scene, const DevView* views, int n_views,
+                                   const float* records, const float* grad2d, hipStream_t st) {
+  const int C = S.dim - 3;
+  if (S.rot == UBS_ROT_QUAT) {
+    if (C == 0) return pre_bwd_t<T, 0, 0>(S, scene, views, n_views, records, grad2d, st);
+    if (C == 3) return pre_bwd_t<T, 3, 0>(S, scene, views, n_views, records, grad2d, st);
+    if (C == 4) return pre_bwd_t<T, 4, 0>(S, scene, views, n_views, records, grad2d, st);
+  } else {
+    if (C == 0) return pre_bwd_t<T, 0, 1>(S, scene, views, n_views, records, grad2d, st);
+    if (C == 3) return pre_bwd_t<T, 3, 1>(S, scene, views, n_views, records, grad2d, st);
+    if (C == 4) return pre_bwd_t<T, 4, 1>(S, scene, views, n_views, records, grad2d, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_preprocess_fwd(bool fp64, const DevScene& S, int scene, const DevView* views,
+                                 int n_views, float* records, DevStatus* status, hipStream_t st) {
+  if (S.n == 0) return hipSuccess;
+  return fp64 ? pre_fwd_dispatch<double>(S, scene, views, n_views, records, status, st)
+              : pre_fwd_dispatch<float>(S, scene, views, n_views, records, status, st);
+}
+
+hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const DevView* views,
+                                 int n_views, const float* records, const float* grad2d,
+                                 hipStream_t st) {
+  if (S.n == 0) return hipSuccess;
+  return fp64 ? pre_bwd_dispatch<double>(S, scene, views, n_views, records, grad2d, st)
+              : pre_bwd_dispatch<float>(S, scene, views, n_views, records, grad2d, st);
+}
+
+}  // namespace ubs

@@ -1,0 +1,106 @@
+// Internal definitions shared by the HIP translation units of libubs.
+// Not part of the public ABI (include/ubs.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ubs.h"
+
+namespace ubs {
+
+constexpr int kRecFloats = 12;   // record: mx my a b c rho o beta r g b depth
+constexpr int kGradFloats = 10;  // d mx, my, a, b, c, o, beta, r, g, b
+constexpr float kNear = 0.2f;
+constexpr float kDilation = 0.3f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTStop = 1e-4f;
+
+// Per-view constants as the kernels read them (copied into the workspace).
+struct DevView {
+  float R[9];
+  float t[3];
+  float cam[3];          // camera centre -R^T t
+  float fx, fy, cx, cy;
+  float time;
+  int32_t scene;
+  int32_t W, H;
+  int32_t tiles_x, tiles_y;
+  int32_t tile_w, tile_h;
+  uint32_t tile_base;    // first global tile of the view
+  uint32_t rec_base;     // first record of the view
+  uint32_t pix_base;     // first pixel of the view
+  uint32_t _pad[2];
+};
+static_assert(sizeof(DevView) % 16 == 0, "DevView alignment");
+
+struct DevScene {
+  const float* params;
+  float* dparams;
+  int64_t n;
+  int32_t dim, rot, F;
+  int32_t _pad;
+};
+
+// Row offsets of the parameter format (component-major [F][n]).
+struct ParamRows {
+  int mu_x, mu_q, rot, log_s, lqx, lq, b_x, b_q, o, rgb, F;
+};
+
+__host__ __device__ inline ParamRows param_rows(int C, int rot) {
+  ParamRows r;
+  int k = 0;
+  r.mu_x = k; k += 3;
+  r.mu_q = k; k += C;
+  r.rot = k; k += (rot == UBS_ROT_QUAT ? 4 : 3);
+  r.log_s = k; k += 3;
+  r.lqx = k; k += 3 * C;
+  r.lq = k; k += C * (C + 1) / 2;
+  r.b_x = k; k += 1;
+  r.b_q = k; k += C;
+  r.o = k; k += 1;
+  r.rgb = k; k += 3;
+  r.F = k;
+  return r;
+}
+
+// Status block, mirrors ubs_status_block.
+struct DevStatus {
+  unsigned long long pairs_needed;
+  uint32_t overflow;
+  uint32_t n_nonfinite;
+  uint32_t n_visible;
+  uint32_t work_counter[3];  // persistent raster queues (fwd, bwd, spare)
+  uint32_t _pad[8];
+};
+static_assert(sizeof(DevStatus) == sizeof(ubs_status_block), "status block size");
+
+// Full private layout of the workspace (superset of ubs_layout).
+struct Layout {
+  ubs_layout pub;
+  uint64_t off_views, off_scenes, off_counts, off_offsets, off_blocksums;
+  uint64_t off_keys_alt, off_values_alt, off_hist;
+  uint64_t off_keys0, off_values0;  // ping-pong buffer 0
+  uint64_t off_tfinal_ws;            // final transmittance kept for the adjoint
+  int64_t n_scan_blocks;
+  int64_t n_sort_blocks;
+  int32_t n_passes, digit_bits;
+  int32_t tile_w, tile_h;
+};
+
+// Scan / sort geometry.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;                       // per thread
+constexpr int kScanTile = kScanThreads * kScanItems; // 4096 per block
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;                        // per lane
+constexpr int kSortTile = kSortThreads * kSortItems; // 2048 per block
+
+inline int ceil_log2_u64(uint64_t x) {
+  int b = 0;
+  while ((1ull << b) < x) ++b;
+  return b;
+}
+
+}  // namespace ubs

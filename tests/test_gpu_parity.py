@@ -1,0 +1,375 @@
+"""Parity of the HIP path with the fp64 oracle, through the C ABI.
+
+Bars: tile keys, sort order and per-tile ranges bit-exact (given identical
+float32 records); pixels within 1e-4 max-abs; gradients within 1e-3
+relative (floor 1e-3 of the block's largest entry).  Pixels that the oracle
+flags as threshold-ambiguous (see oracle/raster.c) are excluded and counted.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from _gpu_common import (GRAD_BLOCKS, bin_reference, compare_images, gpu_ready, gpu_render,
+                         grad_violations, log, oracle_view, to_dev)
+from oracle import preprocess as opp
+from oracle import raster as oraster
+from synth import look_at_view, make_config, make_splat_records, make_view
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_ready(), reason="needs a GPU")]
+
+CASES = {
+    "cfg0_3d_quat": ("cfg0", dict(n=2000)),
+    "cfg0_3d_skew_ragged": ("cfg0", dict(n=1500, rot=1, width=100, height=90)),
+    "cfg1_6d_ragged": ("cfg1", dict(n=20000, width=200, height=136)),
+    "cfg1_6d_skew": ("cfg1", dict(n=12000, width=96, height=160, rot=1)),
+    "headline_7d_ragged": ("headline", dict(n=30000, width=240, height=135)),
+}
+
+
+def _dump(name, **arrays):
+    import os
+    os.makedirs("gpurun_out", exist_ok=True)
+    np.savez_compressed(os.path.join("gpurun_out", name + ".npz"), **arrays)
+
+
+def _cfg(name):
+    base, kw = CASES[name]
+    return make_config(base, **kw)
+
+
+# ------------------------------------------------------------------ preprocess
+@pytest.mark.parametrize("case", list(CASES))
+def test_preprocess_records_match_oracle(case):
+    log(f"[preprocess] {case}")
+    cfg = _cfg(case)
+    g = gpu_render(cfg)
+    o = oracle_view(cfg, 0)
+    rg, ro = g["records"], o["rec"]
+    vg, vo, amb = rg[:, 5] > 0, o["valid"], o["amb"]
+    mism = (vg != vo) & ~amb
+    assert mism.sum() == 0, np.flatnonzero(mism)[:10]
+    both = vg & vo
+    assert both.sum() > 50
+    for k, name in enumerate(opp.REC_FIELDS):
+        a, b = rg[both, k].astype(np.float64), ro[both, k]
+        scale = np.median(np.abs(b)) + 1e-12
+        err = np.abs(a - b) / (np.abs(b) + scale)
+        assert err.max() < 2e-5, (name, err.max())
+    assert g["status"]["n_visible"] == int(vg.sum())
+    assert g["status"]["n_nonfinite"] == 0
+
+
+# ------------------------------------------------------------------ bin + sort
+def _inject_and_sort(cfg, recs):
+    from paper_2510_03312_amd import Renderer, SceneRef, Tuning
+    r = Renderer(Tuning(pair_capacity=1 << 20))
+    scenes = [SceneRef(to_dev(s.params), s.dim, s.rot) for s in cfg["scenes"]]
+    frame = r.make_frame(scenes, cfg["views"])
+    r.preprocess(frame)
+    r.records().copy_(to_dev(recs))
+    r.bin_sort(frame)
+    st = r.status()
+    K = st["pairs_needed"]
+    keys, vals = r.sorted_pairs(K)
+    return r, frame, K, keys.cpu().numpy().view(np.uint64), vals.cpu().numpy().view(np.uint32), \
+        r.ranges().cpu().numpy().view(np.uint32)
+
+
+class _V:
+    def __init__(self, v, n):
+        self.width, self.height, self.n_records = v.width, v.height, n
+
+
+@pytest.mark.parametrize("n,W,H,seed", [(3000, 200, 150, 1), (500, 37, 23, 2), (4000, 1280, 720, 3)])
+def test_bin_sort_bit_exact_on_identical_records(n, W, H, seed):
+    log(f"[bin_sort] n={n} {W}x{H}")
+    cfg = make_config("cfg0", n=n, width=W, height=H)
+    recs = make_splat_records(n, W, H, seed=seed, max_extent=min(60.0, W / 4))
+    recs[:20, 11] = recs[20:40, 11]          # exact depth ties
+    r, frame, K, keys, vals, ranges = _inject_and_sort(cfg, recs)
+    sk, sv, rg = bin_reference(recs, [_V(cfg["views"][0], n)])
+    assert K == sk.size
+    np.testing.assert_array_equal(keys, sk)
+    np.testing.assert_array_equal(vals, sv)
+    np.testing.assert_array_equal(ranges, rg)
+
+
+def test_bin_sort_bit_exact_multi_view():
+    log("[bin_sort] multi-view")
+    cfg = make_config("cfg4", scene_sizes=(700, 300, 900, 100), n_views=6)
+    for v, (w, h) in zip(cfg["views"], [(64, 48), (100, 30), (33, 17), (128, 128), (16, 16), (90, 70)]):
+        v.width, v.height = w, h
+    ns = [cfg["scenes"][v.scene].n for v in cfg["views"]]
+    recs = np.concatenate([make_splat_records(n, v.width, v.height, seed=10 + k, max_extent=12.0)
+                           for k, (n, v) in enumerate(zip(ns, cfg["views"]))])
+    r, frame, K, keys, vals, ranges = _inject_and_sort(cfg, recs)
+    sk, sv, rg = bin_reference(recs, [_V(v, n) for v, n in zip(cfg["views"], ns)])
+    assert K == sk.size
+    np.testing.assert_array_equal(keys, sk)
+    np.testing.assert_array_equal(vals, sv)
+    np.testing.assert_array_equal(ranges, rg)
+
+
+@pytest.mark.parametrize("digit_bits", [4, 5, 7, 8])
+def test_sort_digit_widths_agree(digit_bits):
+    from paper_2510_03312_amd import Tuning
+    log(f"[bin_sort] digit_bits={digit_bits}")
+    cfg = make_config("cfg0", n=2000, width=300, height=200)
+    recs = make_splat_records(2000, 300, 200, seed=5, max_extent=30.0)
+    sk, sv, rg = bin_reference(recs, [_V(cfg["views"][0], 2000)])
+    from paper_2510_03312_amd import Renderer, SceneRef
+    r = Renderer(Tuning(pair_capacity=1 << 18, digit_bits=digit_bits))
+    frame = r.make_frame([SceneRef(to_dev(cfg["scenes"][0].params), 3, 0)], cfg["views"])
+    r.preprocess(frame)
+    r.records().copy_(to_dev(recs))
+    r.bin_sort(frame)
+    K = r.status()["pairs_needed"]
+    keys, vals = r.sorted_pairs(K)
+    np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint64), sk)
+    np.testing.assert_array_equal(vals.cpu().numpy().view(np.uint32), sv)
+
+
+# ------------------------------------------------------------------ forward
+@pytest.mark.parametrize("case", list(CASES))
+def test_render_forward_matches_oracle(case):
+    log(f"[fwd] {case}")
+    cfg = _cfg(case)
+    g = gpu_render(cfg)
+    o = oracle_view(cfg, 0)
+    err, nflag, nbad = compare_images(g["images"][0], o["image"], o["flags"], 1e-4)
+    log(f"  max err {err:.3g}, flagged {nflag}, bad {nbad}")
+    assert nbad == 0 and err <= 1e-4
+    terr, _, tbad = compare_images(g["t_final"][0], o["t_final"], o["flags"], 1e-4)
+    assert tbad == 0
+    assert nflag <= 0.01 * o["flags"].size
+
+
+def test_raster_only_parity_on_identical_records():
+    """Identical float32 records on both sides isolate the compositing."""
+    log("[fwd] raster only")
+    W, H, n = 160, 120, 1500
+    cfg = make_config("cfg0", n=n, width=W, height=H)
+    recs = make_splat_records(n, W, H, seed=7, max_extent=25.0)
+    r, frame, K, keys, vals, ranges = _inject_and_sort(cfg, recs)
+    img = torch.empty((W * H, 3), device="cuda")
+    tf = torch.empty((W * H,), device="cuda")
+    r.render_fwd(frame, img, tf)
+    o_img, o_tf, o_nc, o_fl = oraster.render_fwd(recs.astype(np.float64), W, H)
+    gi = img.view(H, W, 3).cpu().numpy()
+    err, nflag, nbad = compare_images(gi, o_img, o_fl, 1e-5)
+    log(f"  max err {err:.3g}, flagged {nflag}")
+    assert nbad == 0
+    # adjoint of the compositing alone: d_image zero at flagged pixels
+    rng = np.random.default_rng(0)
+    dimg = rng.normal(size=(H, W, 3)) * (o_fl == 0)[..., None]
+    dtf = rng.normal(size=(H, W)) * (o_fl == 0)
+    d_rec, d_abs = oraster.render_bwd(recs.astype(np.float64), W, H, dimg, dtf, with_abs=True)
+    dparams = torch.empty_like(frame.scenes[0].params)
+    frame.set_dparams(0, dparams)
+    r.render_bwd(frame, to_dev(dimg.astype(np.float32)).view(-1, 3),
+                 to_dev(dtf.astype(np.float32)).view(-1))
+    g2 = r.grad2d().cpu().numpy()
+    for k in range(10):
+        v = grad_violations(g2[:, k], d_rec[:, k], noise=d_abs[:, k])
+        assert v.sum() == 0, (k, np.flatnonzero(v)[:5], g2[v, k][:5], d_rec[v, k][:5])
+
+
+# ------------------------------------------------------------------ backward
+def _block_slices(dim, rot):
+    sl = opp.field_slices(dim, rot)
+    return {k: sl[k] for k in GRAD_BLOCKS if sl[k].stop > sl[k].start}
+
+
+@pytest.mark.parametrize("case", ["cfg0_3d_quat", "cfg0_3d_skew_ragged", "cfg1_6d_ragged",
+                                  "cfg1_6d_skew", "headline_7d_ragged"])
+def test_gradients_match_oracle(case):
+    log(f"[bwd] {case}")
+    cfg = _cfg(case)
+    view = cfg["views"][0]
+    o0 = oracle_view(cfg, 0)
+    rng = np.random.default_rng(3)
+    ok = (o0["flags"] == 0)
+    dimg = rng.normal(size=(view.height, view.width, 3)) * ok[..., None] / math.sqrt(ok.size)
+    o = oracle_view(cfg, 0, d_image=dimg)
+    g = gpu_render(cfg, want_grad=True, d_images=[dimg])
+    sc = cfg["scenes"][0]
+    _dump(f"grad_{case}", dparams=g["dparams"][0], grad2d=g["grad2d"], records=g["records"],
+          ref=o["dparams"], d_rec=o["d_rec"], noise=o["dparams_noise"], dimg=dimg)
+    total_bad = 0
+    for name, s in _block_slices(sc.dim, sc.rot).items():
+        gg, go = g["dparams"][0][s], o["dparams"][s]
+        v = grad_violations(gg, go, noise=o["dparams_noise"][s])
+        log(f"  {name}: strict-relative violations {int(grad_violations(gg, go).sum())}")
+        log(f"  {name}: max|ref| {np.abs(go).max():.3g} violations {int(v.sum())}")
+        for r_, c_ in list(zip(*np.nonzero(v)))[:4]:
+            log(f"    row {s.start + r_} prim {c_}: gpu {gg[r_, c_]:.6g} ref {go[r_, c_]:.6g}")
+        total_bad += int(v.sum())
+    assert total_bad == 0
+
+
+def test_fused_l1_gradient_equals_explicit():
+    log("[bwd] fused L1")
+    cfg = make_config("cfg0", n=1000, width=96, height=80)
+    a = gpu_render(cfg, want_grad=True, l1=True)
+    img = a["images"][0].astype(np.float64)
+    d = np.sign(img - cfg["targets"][0]) / img.size
+    b = gpu_render(cfg, want_grad=True, d_images=[d])
+    np.testing.assert_allclose(a["dparams"][0], b["dparams"][0], rtol=1e-5, atol=1e-12)
+
+
+def test_gradients_match_finite_differences_on_subscene():
+    """64 primitives, 32x32 crop at the centre of the 1920x1080 6-D workload."""
+    log("[bwd] FD sub-scene")
+    full = make_config("cfg2", n=200_000)
+    sc = full["scenes"][0]
+    view = full["views"][0]
+    x0, y0 = 944, 524
+    crop = look_at_view((0.0, 0.0, -4.0), 1920, 1080)
+    crop.width, crop.height = 32, 32
+    crop.cx, crop.cy = view.cx - x0, view.cy - y0
+    P = torch.tensor(sc.params.astype(np.float64))
+    out = opp.preprocess(P, sc.dim, sc.rot, crop)
+    rec = out["rec"].numpy()
+    valid = out["valid"].numpy()
+    ext = np.sqrt(np.maximum(rec[:, 4], 1e-30) / np.maximum(rec[:, 2] * rec[:, 4] - rec[:, 3] ** 2, 1e-30))
+    eyt = np.sqrt(np.maximum(rec[:, 2], 1e-30) / np.maximum(rec[:, 2] * rec[:, 4] - rec[:, 3] ** 2, 1e-30))
+    hit = valid & (rec[:, 0] + ext > 0) & (rec[:, 0] - ext < 32) & (rec[:, 1] + eyt > 0) & (rec[:, 1] - eyt < 32)
+    idx = np.flatnonzero(hit)[:64]
+    assert idx.size == 64
+    sub = np.ascontiguousarray(sc.params[:, idx])
+    cfg = {"scenes": [type(sc)(dim=sc.dim, rot=sc.rot, params=sub)], "views": [crop],
+           "targets": [np.zeros((32, 32, 3), np.float32)]}
+    rng = np.random.default_rng(9)
+    o0 = oracle_view(cfg, 0)
+    wimg = rng.normal(size=(32, 32, 3)) * (o0["flags"] == 0)[..., None]
+    o = oracle_view(cfg, 0, d_image=wimg)
+    g = gpu_render(cfg, want_grad=True, d_images=[wimg])
+    from oracle import render as orender
+    P64 = sub.astype(np.float64)
+    scale = np.abs(o["dparams"]).max()
+    checked = 0
+    for f in range(P64.shape[0]):
+        for i in rng.choice(64, size=4, replace=False):
+            h = 1e-6 * max(1.0, abs(P64[f, i]))
+            fd = []
+            for hh in (h, h / 2):
+                Pp, Pm = P64.copy(), P64.copy()
+                Pp[f, i] += hh
+                Pm[f, i] -= hh
+                fd.append((orender.loss_value(Pp, sc.dim, sc.rot, crop, wimg)
+                           - orender.loss_value(Pm, sc.dim, sc.rot, crop, wimg)) / (2 * hh))
+            if abs(fd[0] - fd[1]) > 1e-6 * max(abs(fd[1]), 1e-3 * scale):
+                continue
+            gv = float(g["dparams"][0][f, i])
+            assert abs(gv - fd[1]) <= 1e-3 * max(abs(fd[1]), 1e-3 * scale), (f, i, gv, fd[1])
+            checked += 1
+    log(f"  checked {checked} FD entries")
+    assert checked > 60
+
+
+# ------------------------------------------------------------------ edge cases
+def test_empty_scene_and_tiny_images():
+    log("[edge] empty / 1x1")
+    cfg = make_config("cfg0", n=10, width=1, height=1)
+    cfg["scenes"][0].params = cfg["scenes"][0].params[:, :0].copy()
+    g = gpu_render(cfg, want_grad=True, d_images=[np.ones((1, 1, 3))])
+    assert g["images"][0].shape == (1, 1, 3)
+    assert np.all(g["images"][0] == 0) and np.all(g["t_final"][0] == 1)
+    cfg = make_config("cfg0", n=50, width=1, height=1)
+    g = gpu_render(cfg)
+    o = oracle_view(cfg, 0)
+    assert abs(g["images"][0] - o["image"]).max() <= 1e-4
+
+
+def test_everything_culled_behind_camera():
+    log("[edge] all culled")
+    cfg = make_config("cfg0", n=500, width=64, height=64)
+    v = make_view(64, 64)
+    v.t = np.array([0.0, 0.0, -10.0], np.float32)   # camera at z = +10 looking along +z
+    cfg["views"] = [v]
+    g = gpu_render(cfg, want_grad=True, d_images=[np.ones((64, 64, 3))])
+    assert g["status"]["pairs_needed"] == 0
+    assert np.all(g["images"][0] == 0)
+    assert np.all(g["dparams"][0] == 0)
+
+
+def test_nonfinite_parameters_are_culled_and_counted():
+    log("[edge] non-finite")
+    cfg = make_config("cfg0", n=800, width=64, height=64)
+    P = cfg["scenes"][0].params
+    P[0, 5] = np.nan
+    P[7, 9] = np.inf
+    g = gpu_render(cfg)
+    assert g["status"]["n_nonfinite"] == 2
+    keep = np.ones(800, bool)
+    keep[[5, 9]] = False
+    cfg2 = make_config("cfg0", n=800, width=64, height=64)
+    cfg2["scenes"][0].params = np.ascontiguousarray(P[:, keep])
+    h = gpu_render(cfg2)
+    np.testing.assert_array_equal(g["images"][0], h["images"][0])
+
+
+def test_pair_overflow_is_flagged_and_recovered():
+    from paper_2510_03312_amd import Renderer, SceneRef, Tuning
+    log("[edge] overflow")
+    cfg = make_config("cfg0", n=2000)
+    scenes = [SceneRef(to_dev(cfg["scenes"][0].params), 3, 0)]
+    r = Renderer(Tuning(pair_capacity=64))
+    frame = r.make_frame(scenes, cfg["views"])
+    r.preprocess(frame)
+    r.bin_sort(frame)
+    st = r.status()
+    assert st["overflow"] == 1 and st["pairs_needed"] > 64
+    img = torch.empty((128 * 128, 3), device="cuda")
+    r.render_fwd(frame, img, None)
+    torch.cuda.synchronize()
+    assert float(img.abs().max()) == 0.0        # nothing drawn, nothing faulted
+    img2, _ = r.forward(scenes, cfg["views"])   # grows the capacity and reruns
+    assert r.capacity >= st["pairs_needed"]
+    ref = gpu_render(cfg)
+    np.testing.assert_array_equal(img2.view(128, 128, 3).cpu().numpy(), ref["images"][0])
+
+
+# ------------------------------------------------------------------ batching
+def test_batched_views_equal_single_views():
+    log("[batch] cfg3-like, 8 views")
+    cfg = make_config("cfg3", n=20000, width=160, height=120)
+    g = gpu_render(cfg, want_grad=True, d_images=[np.full((120, 160, 3), 1e-3)] * 8)
+    acc = np.zeros_like(g["dparams"][0], dtype=np.float64)
+    for k, v in enumerate(cfg["views"]):
+        one = {"scenes": cfg["scenes"], "views": [v], "targets": [cfg["targets"][k]]}
+        s = gpu_render(one, want_grad=True, d_images=[np.full((120, 160, 3), 1e-3)])
+        np.testing.assert_array_equal(g["images"][k], s["images"][0])
+        np.testing.assert_array_equal(g["t_final"][k], s["t_final"][0])
+        acc += s["dparams"][0]
+    # fp32 atomics accumulate in a different order: compare at 1e-4
+    v = grad_violations(g["dparams"][0], acc, rtol=1e-4, floor=1e-4)
+    assert v.sum() == 0
+
+
+def test_batched_uneven_multi_scene_matches_oracle():
+    log("[batch] cfg4-like uneven")
+    cfg = make_config("cfg4", scene_sizes=(3000, 6000, 9000, 12000), n_views=6)
+    sizes = [(96, 64), (64, 48), (128, 72), (80, 80), (48, 96), (112, 63)]
+    for v, (w, h) in zip(cfg["views"], sizes):
+        v.width, v.height, v.cx, v.cy = w, h, w / 2, h / 2
+        v.fx = v.fy = float(np.float32((w / 2) / math.tan(math.radians(30))))
+    g = gpu_render(cfg)
+    for k in range(len(cfg["views"])):
+        o = oracle_view(cfg, k)
+        err, nflag, nbad = compare_images(g["images"][k], o["image"], o["flags"], 1e-4)
+        assert nbad == 0, (k, err)
+
+
+def test_determinism():
+    log("[det] two runs")
+    cfg = make_config("headline", n=30000, width=240, height=135)
+    a = gpu_render(cfg, want_grad=True, d_images=[np.full((135, 240, 3), 1e-3)])
+    b = gpu_render(cfg, want_grad=True, d_images=[np.full((135, 240, 3), 1e-3)])
+    np.testing.assert_array_equal(a["images"][0], b["images"][0])
+    np.testing.assert_array_equal(a["records"], b["records"])
+    v = grad_violations(a["dparams"][0], b["dparams"][0].astype(np.float64), rtol=1e-5, floor=1e-4)
+    assert v.sum() == 0
