@@ -5,11 +5,16 @@ One step = one full forward+backward frame through the four C entry points
 (preprocess -> bin_sort -> render_fwd -> render_bwd with the fused L1 loss
 gradient), on inputs already resident in HBM.  Default workload: 1,000,000
 7-D Beta primitives (quaternion rotation), one 1920x1080 view at t = 0.5,
-L1 loss against a seeded U(0,1) target.
+L1 loss against a seeded U(0,1) target.  The timed steps replay HIP graphs
+of the frame (``--eager`` times the plain calls instead).
 
 Prints ONE JSON line.  Per-stage kernel durations come from HIP events that
 the library records around each stage inside the timed region (on the stream
 the kernels run on); the roofline object reports the dominant stage.
+
+``--workload cfg3`` / ``cfg4`` time the batched multi-view frames (views/s),
+``cfg4`` with the autotuner's tuning, each beside the same views rendered one
+per frame through the single-view path.
 """
 from __future__ import annotations
 
@@ -28,15 +33,48 @@ METRIC = "fwd+bwd frames/s at 1M 7-D Beta prims, 1080p, 1 MI355X; % HBM roofline
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
-    "headline": ("headline", {}, "1,000,000 7-D Beta primitives (quaternion rotation), one "
-                                 "1920x1080 view at t=0.5, forward+backward, L1 loss"),
-    "cfg2": ("cfg2", {}, "1,000,000 6-D Beta primitives, one 1920x1080 view, forward+backward, L1 loss"),
-    "cfg0": ("cfg0", {}, "2,000 3-D Beta primitives, one 128x128 view, forward+backward, L1 loss"),
+    "headline": ("headline", "1,000,000 7-D Beta primitives (quaternion rotation), one "
+                             "1920x1080 view at t=0.5, forward+backward, L1 loss"),
+    "cfg2": ("cfg2", "1,000,000 6-D Beta primitives, one 1920x1080 view, forward+backward, L1 loss"),
+    "cfg1": ("cfg1", "500,000 6-D Beta primitives, one 1264x832 view, forward only"),
+    "cfg0": ("cfg0", "2,000 3-D Beta primitives, one 128x128 view, forward+backward, L1 loss"),
+    "cfg3": ("cfg3", "2,000,000 7-D Beta primitives, 8 views of 1352x1014 (cameras on a circle, "
+                     "t = k/7) in one batched frame, forward+backward, L1 loss"),
+    "cfg4": ("cfg4", "4 scenes of 7-D Beta primitives (100k/500k/1.5M/3M), 32 views of uneven "
+                     "resolution in one batched frame, autotuned, forward+backward, L1 loss"),
 }
 
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_sources_digest() -> str:
+    """sha256 over the HIP sources and the ABI header (a profile's counters
+    describe the kernels built from exactly these sources)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2510_03312_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")))
+    files.append(os.path.join(ROOT, "include", "ubs.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary in profiles/, if it was taken on the current sources."""
+    import re
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    digest = kernel_sources_digest()
+    for m in re.finditer(r"<!-- traffic kernel=(\w+) bytes=(\d+) sources=(\w+) -->", open(path).read()):
+        if m.group(1) == kernel and m.group(3) == digest:
+            return int(m.group(2))
+    return None
 
 
 def stage_bytes(stage: str, c: dict) -> float:
@@ -53,7 +91,9 @@ def stage_bytes(stage: str, c: dict) -> float:
         "raster_fwd": 52.0 * K + 20.0 * A + 8.0 * G,
         "grad_clear": 40.0 * R,
         "raster_bwd": 92.0 * K + 32.0 * A + 8.0 * G,
-        "pre_bwd": 8.0 * F * P + 4.0 * R + 40.0 * Pv,
+        # live primitives' parameters read (Pv bounds them), every gradient
+        # written, liveness flags and the live records' gradients read
+        "pre_bwd": 4.0 * F * Pv + 4.0 * F * P + 8.0 * R + 40.0 * Pv,
     }[stage]
 
 
@@ -97,106 +137,194 @@ def cpu_baseline(cfg, rows: int = 24, sub: int = 100_000) -> dict:
                        f"x{H / (band[1] - band[0]):g}; float64, 1 thread")}
 
 
+def timed_steps(gf, steps: int, eager: bool):
+    """Times `steps` frames; returns (ms per step, per-stage mean ms).  With
+    graphs, step k replays a graph captured with stage-event slot k."""
+    import numpy as np
+    import torch
+    from paper_2510_03312_amd.timing import StageTimer
+
+    timer = StageTimer(steps)
+    stream = torch.cuda.current_stream()
+    graphs = None if eager else [gf.capture(timer.slot(k)) for k in range(steps)]
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(steps):
+        if eager:
+            timer.attach(gf.frame.c, k)
+            gf.step()
+        else:
+            graphs[k].replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    timer.detach(gf.frame.c)
+    ms = e0.elapsed_time(e1) / steps
+    stages = {}
+    for k in range(steps):
+        for s, v in timer.elapsed_ms(k).items():
+            stages.setdefault(s, []).append(v)
+    timer.close()
+    return ms, {s: float(np.mean(v)) for s, v in stages.items()}
+
+
+def run_single(args, name, desc):
+    import torch
+    from paper_2510_03312_amd import Renderer, SceneRef, Tuning, UBS_TUNE_PRE_FP32
+    from paper_2510_03312_amd.renderer import GraphFrame
+    from synth import make_config
+
+    cfg = make_config(name)
+    sc, view = cfg["scenes"][0], cfg["views"][0]
+    dev = torch.device("cuda:0")
+    params = torch.from_numpy(sc.params).to(dev)
+    target = torch.from_numpy(cfg["targets"][0]).to(dev).view(-1, 3).contiguous()
+    backward = cfg["mode"] == "fwdbwd"
+    r = Renderer(Tuning(flags=UBS_TUNE_PRE_FP32 if args.pre_fp32 else 0))
+    log("[bench] sizing and capturing the frame")
+    gf = GraphFrame(r, [SceneRef(params, sc.dim, sc.rot)], [view],
+                    l1_target=target if backward else None, backward=backward)
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    for _ in range(args.warmup):
+        gf.step() if args.eager else gf.replay()
+    torch.cuda.synchronize()
+    st = r.status()
+    assert not st["overflow"] and not st["sort_stalled"], st
+    log(f"[bench] pairs {st['pairs_needed']:,} visible {st['n_visible']:,}; timing {args.steps} steps")
+    t_wall = time.perf_counter()
+    ms, stages_ms = timed_steps(gf, args.steps, args.eager)
+    t_wall = time.perf_counter() - t_wall
+    st = r.status()
+    assert not st["overflow"] and not st["sort_stalled"], st
+    lay = r.layout
+    c = {"P": sc.n, "F": int(sc.params.shape[0]), "R": lay.n_records, "Pv": st["n_visible"],
+         "K": st["pairs_needed"], "A": lay.n_pixels, "G": lay.n_tiles,
+         "passes": math.ceil(lay.key_bits / r.tuning.digit_bits)}
+    dom = max(stages_ms, key=stages_ms.get)
+    ach = stage_bytes(dom, c) / (stages_ms[dom] * 1e-3) / 1e9
+    frame_bytes = sum(stage_bytes(s, c) for s in stages_ms)
+    res = {
+        "metric": METRIC if name == "headline" else f"{'fwd+bwd' if backward else 'fwd'} frames/s ({name})",
+        "value": round(1000.0 / ms, 3), "unit": "frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "primitives": sc.n, "dim": sc.dim, "params_per_prim": c["F"],
+                   "width": view.width, "height": view.height, "views": 1, "pairs": c["K"],
+                   "visible": c["Pv"], "launch": "eager" if args.eager else "hip-graph"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
+                     "traffic": recorded_traffic(name, dom)},
+        "kernel_sources": kernel_sources_digest(),
+        "frame_hbm_frac": round(frame_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+        "stages_ms": {k: round(v, 4) for k, v in stages_ms.items()},
+        "per_primitive_math": "f32" if args.pre_fp32 else "f64",
+        "wall_s": round(t_wall, 3),
+    }
+    if not args.no_cpu_baseline and name == "headline":
+        log("[bench] timing the oracle on a bounded CPU sample")
+        res["cpu_baseline"] = cpu_baseline(cfg)
+        res["cpu_baseline"]["value"] = round(res["cpu_baseline"]["value"], 6)
+    return res
+
+
+def run_batched(args, name, desc):
+    import torch
+    from paper_2510_03312_amd import Renderer, SceneRef, Tuning
+    from paper_2510_03312_amd.autotune import autotune
+    from paper_2510_03312_amd.renderer import GraphFrame
+    from synth import make_config
+
+    cfg = make_config(name)
+    dev = torch.device("cuda:0")
+    scenes = [SceneRef(torch.from_numpy(s.params).to(dev), s.dim, s.rot) for s in cfg["scenes"]]
+    views = cfg["views"]
+    target = torch.cat([torch.from_numpy(t).view(-1, 3) for t in cfg["targets"]]).to(dev)
+    tuning, tune_ms = Tuning(), None
+    if name == "cfg4":
+        log("[bench] autotuning")
+        tuning, tune_ms = autotune(scenes, views, l1_target=target, steps=2)
+    batched, single = {}, {}
+    for mode in ("fwdbwd", "fwd"):
+        backward = mode == "fwdbwd"
+        log(f"[bench] batched {mode}")
+        gf = GraphFrame(Renderer(Tuning(**tuning.__dict__)), scenes, views,
+                        l1_target=target if backward else None, backward=backward)
+        for _ in range(args.warmup):
+            gf.replay()
+        ms, stages = timed_steps(gf, args.steps, args.eager)
+        st = gf.status()
+        assert not st["overflow"] and not st["sort_stalled"], st
+        batched[mode] = {"views_per_s": round(len(views) * 1000.0 / ms, 2), "ms_per_frame": round(ms, 4),
+                         "stages_ms": {k: round(v, 4) for k, v in stages.items()}}
+        del gf
+        torch.cuda.empty_cache()
+        # the same views one per frame through the single-view path
+        log(f"[bench] single-view path {mode}")
+        frames, base = [], 0
+        for v in views:
+            n = v.width * v.height
+            tv = target[base:base + n].contiguous()
+            base += n
+            frames.append(GraphFrame(Renderer(Tuning(**tuning.__dict__)), scenes, [v],
+                                     l1_target=tv if backward else None, backward=backward))
+        reps = max(1, args.steps // 4)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            for f in frames:
+                f.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        single[mode] = {"views_per_s": round(len(views) * 1000.0 / ms, 2), "ms_per_batch": round(ms, 4)}
+        del frames
+        torch.cuda.empty_cache()
+    return {
+        "metric": f"batched fwd+bwd views/s ({name})", "value": batched["fwdbwd"]["views_per_s"],
+        "unit": "views/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": batched["fwdbwd"]["ms_per_frame"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": desc, "views": len(views), "scenes": len(scenes),
+                   "primitives": [s.n for s in scenes],
+                   "tuning": {"tile": [tuning.tile_w, tuning.tile_h],
+                              "batch_depth": tuning.batch_depth, "persistent": bool(tuning.flags & 1)}},
+        "batched": batched, "single_view_path": single, "autotune_ms": tune_ms,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="headline", choices=sorted(WORKLOADS))
+    ap.add_argument("--eager", action="store_true", help="time plain calls instead of graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pre-fp32", action="store_true",
+                    help="per-primitive math in float32 instead of float64")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="before timing, run a 256 MiB device copy (torch) whose known "
+                         "traffic calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the renderer "
-              "shards by view across GPUs but this build runs and reports a single MI355X.",
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): this build runs "
+              "and reports a single MI355X; multi-GPU sharding by view is a design note only.",
               file=sys.stderr)
         return 2
-
-    import numpy as np
     import torch
-
-    from paper_2510_03312_amd import Renderer, SceneRef, Tuning
-    from paper_2510_03312_amd import _lib
-    from paper_2510_03312_amd.timing import StageTimer
-    from synth import make_config
-
-    name, kw, desc = WORKLOADS[args.workload]
-    log(f"[bench] building workload {args.workload}")
-    cfg = make_config(name, **kw)
-    sc, view = cfg["scenes"][0], cfg["views"][0]
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    params = torch.from_numpy(sc.params).to(dev)
-    target = torch.from_numpy(cfg["targets"][0]).to(dev).view(-1, 3).contiguous()
-    r = Renderer(Tuning())
-    scenes = [SceneRef(params, sc.dim, sc.rot)]
-    dparams = torch.empty_like(params)
-    log("[bench] sizing the frame")
-    image, t_final = r.forward(scenes, [view])          # grows the pair capacity if needed
-    frame = r.frame
-    frame.set_dparams(0, dparams)
-    st = r.status()
-    log(f"[bench] pairs {st['pairs_needed']:,} visible {st['n_visible']:,} capacity {r.capacity:,}")
-
-    def step():
-        r.preprocess(frame)
-        r.bin_sort(frame)
-        r.render_fwd(frame, image, t_final)
-        r.render_bwd(frame, l1_image=image, l1_target=target)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    st = r.status()
-    assert not st["overflow"], st
-    timer = StageTimer(args.steps)
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    log(f"[bench] timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    e0.record(stream)
-    for k in range(args.steps):
-        timer.attach(frame.c, k)
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
-    StageTimer.detach(frame.c)
-    ms_per_step = e0.elapsed_time(e1) / args.steps
-    stages = {}
-    for k in range(args.steps):
-        for s, ms in timer.elapsed_ms(k).items():
-            stages.setdefault(s, []).append(ms)
-    stages_ms = {s: float(np.mean(v)) for s, v in stages.items()}
-    timer.close()
-    st = r.status()
-    lay = r.layout
-    counts = {"P": sc.n, "F": sc.params.shape[0], "R": lay.n_records, "Pv": st["n_visible"],
-              "K": st["pairs_needed"], "A": lay.n_pixels, "G": lay.n_tiles,
-              "passes": math.ceil(lay.key_bits / r.tuning.digit_bits)}
-    dom = max(stages_ms, key=stages_ms.get)
-    ach = stage_bytes(dom, counts) / (stages_ms[dom] * 1e-3) / 1e9
-    frame_bytes = sum(stage_bytes(s, counts) for s in stages_ms)
-    value = 1000.0 / ms_per_step
-    res = {
-        "metric": METRIC, "value": round(value, 3), "unit": "frames/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": desc, "primitives": sc.n, "dim": sc.dim, "params_per_prim": counts["F"],
-                   "width": view.width, "height": view.height, "views": 1,
-                   "pairs": counts["K"], "visible": counts["Pv"]},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None},
-        "frame_hbm_frac": round(frame_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
-        "stages_ms": {k: round(v, 4) for k, v in stages_ms.items()},
-        "wall_s": round(t_wall, 3),
-    }
-    if not args.no_cpu_baseline:
-        log("[bench] timing the oracle on a bounded CPU sample")
-        res["cpu_baseline"] = cpu_baseline(cfg)
-        res["cpu_baseline"]["value"] = round(res["cpu_baseline"]["value"], 6)
+    torch.cuda.set_device(0)
+    name, desc = WORKLOADS[args.workload]
+    log(f"[bench] workload {args.workload}")
+    res = run_batched(args, name, desc) if name in ("cfg3", "cfg4") else run_single(args, name, desc)
     print(json.dumps(res), flush=True)
     return 0
 

@@ -118,15 +118,17 @@ typedef struct {
 } ubs_view;               /* 96 bytes */
 
 /*
- * Tuning.  tile_w x tile_h in {8x8, 16x8, 16x16, 32x16}; batch_depth in
- * {64, 128, 256, 512} (records staged per LDS batch, rounded to the tile's
- * pixel count); digit_bits in [4, 11] (radix-sort digit width).
+ * Tuning.  tile_w x tile_h in {8x8, 16x8, 16x16, 32x16} (one wavefront of 64
+ * lanes per tile); batch_depth in {64, 128, 256} (records staged in LDS per
+ * round); digit_bits in [4, 8] (radix-sort digit width).
  * pair_capacity: number of (tile, primitive) pairs the workspace holds; if a
  * frame needs more, ubs_bin_sort sets the status overflow flag, emits no
  * pairs and the render calls draw nothing (rerun with a larger capacity,
- * see ubs_status_block.pairs_needed).  flags: UBS_TUNE_* bits.
+ * see ubs_status_block.pairs_needed); at most 2^30 pairs.  flags:
+ * UBS_TUNE_* bits.
  */
-#define UBS_TUNE_PERSISTENT 1u  /* raster through a persistent work queue */
+#define UBS_TUNE_PERSISTENT 1u  /* raster through a persistent grid that takes
+                                   tiles from a work queue (16 wavefronts per CU) */
 #define UBS_TUNE_PRE_FP32 2u    /* per-primitive math in float32 (default float64) */
 typedef struct {
   int32_t tile_w, tile_h;
@@ -214,7 +216,9 @@ typedef struct {
   uint32_t overflow;         /* 1 if pairs_needed > pair_capacity */
   uint32_t n_nonfinite;      /* primitives with non-finite parameters (culled) */
   uint32_t n_visible;        /* records that survived culling */
-  uint32_t _pad[11];
+  uint32_t sort_stalled;     /* 1 if a radix-sort look-back wait hit its bound
+                                (the sorted output is then invalid) */
+  uint32_t _pad[10];
 } ubs_status_block;
 
 /*

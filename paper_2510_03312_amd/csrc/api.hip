@@ -10,14 +10,19 @@
 namespace ubs {
 
 hipError_t launch_preprocess_fwd(bool fp64, const DevScene& S, int scene, const DevView* views,
-                                 int n_views, float* records, DevStatus* status, hipStream_t st);
+                                 int n_views, float* records, uint32_t* live, DevStatus* status,
+                                 hipStream_t st);
 hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const DevView* views,
                                  int n_views, const float* records, const float* grad2d,
-                                 hipStream_t st);
+                                 const uint32_t* live, const uint32_t* offs, const uint32_t* list,
+                                 const unsigned long long* n_live, float* compact, hipStream_t st);
+hipError_t launch_compact(const uint32_t* flags, const uint32_t* offsets, uint32_t n,
+                          uint32_t* list, hipStream_t st);
 hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
                             uint32_t n_records, uint32_t* counts, hipStream_t st);
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
-                       DevStatus* status, unsigned long long capacity, hipStream_t st);
+                       DevStatus* status, unsigned long long capacity, hipStream_t st,
+                       unsigned long long* total_out);
 hipError_t launch_bin_emit(const float* records, const DevView* views, int n_views,
                            uint32_t n_records, const uint32_t* offsets, const DevStatus* status,
                            unsigned long long* keys, uint32_t* values, hipStream_t st);
@@ -25,14 +30,16 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_ranges(const unsigned long long* keys, const DevStatus* status, uint32_t* ranges,
                          size_t n_tiles, unsigned long long capacity, hipStream_t st);
 hipError_t launch_radix_sort(unsigned long long* k0, uint32_t* v0, unsigned long long* k1,
-                             uint32_t* v1, const DevStatus* status, int key_bits, int digit_bits,
-                             uint32_t* hist, uint32_t* tile_sums, uint32_t n_blocks,
+                             uint32_t* v1, DevStatus* status, int key_bits, int digit_bits,
+                             SortState* state, uint32_t* lookback, uint32_t n_blocks,
                              hipStream_t st);
-hipError_t launch_raster_fwd(int tw, int th, const float* records, const uint32_t* values,
+hipError_t launch_raster_fwd(int tw, int th, int batch, uint32_t persistent_blocks,
+                             uint32_t* work, const float* records, const uint32_t* values,
                              const uint32_t* ranges, const DevView* views, int n_views,
                              uint32_t n_tiles, float* image, float* t_ws, float* t_user,
                              uint32_t* ncontrib, hipStream_t st);
-hipError_t launch_raster_bwd(int tw, int th, const float* records, const uint32_t* values,
+hipError_t launch_raster_bwd(int tw, int th, int batch, uint32_t persistent_blocks,
+                             uint32_t* work, const float* records, const uint32_t* values,
                              const uint32_t* ranges, const DevView* views, int n_views,
                              uint32_t n_tiles, const float* t_ws, const uint32_t* ncontrib,
                              const float* d_image, const float* d_tfinal, const float* l1_image,
@@ -58,6 +65,7 @@ __global__ void reset_status_kernel(DevStatus* __restrict__ s) {
     s->overflow = 0;
     s->n_nonfinite = 0;
     s->n_visible = 0;
+    s->sort_stalled = 0;
     s->work_counter[0] = s->work_counter[1] = s->work_counter[2] = 0;
   }
 }
@@ -79,6 +87,17 @@ static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 static bool finite_f(float x) { return isfinite(x) != 0; }
 
+// Persistent raster grid: 16 single-wavefront workgroups per compute unit.
+static uint32_t persistent_blocks(const ubs_frame* f) {
+  if (!(f->tuning.flags & UBS_TUNE_PERSISTENT)) return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return uint32_t(cus > 0 ? cus : 1) * 16u;
+}
+
+static bool batch_ok(int b) { return b == 64 || b == 128 || b == 256; }
+
 static bool tile_ok(int tw, int th) {
   return (tw == 16 && th == 16) || (tw == 16 && th == 8) || (tw == 8 && th == 8) ||
          (tw == 32 && th == 16);
@@ -95,9 +114,11 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   const ubs_tuning& tu = f->tuning;
   if (!tile_ok(tu.tile_w, tu.tile_h)) return UBS_ERR_UNSUPPORTED;
   if (tu.digit_bits < 4 || tu.digit_bits > 8) return UBS_ERR_UNSUPPORTED;
-  if (tu.pair_capacity < 0 || tu.pair_capacity > int64_t(0x7fffffff)) return UBS_ERR_ARG;
+  if (!batch_ok(tu.batch_depth)) return UBS_ERR_UNSUPPORTED;
+  if (tu.pair_capacity < 0 || tu.pair_capacity > int64_t(1) << 30) return UBS_ERR_ARG;
   ds->clear();
   dv->clear();
+  uint64_t n_prims = 0, n_grad_compact = 0;
   for (int s = 0; s < f->n_scenes; ++s) {
     const ubs_scene& S = f->scenes[s];
     if (S.dim < 3 || S.dim > 7) return UBS_ERR_ARG;
@@ -112,6 +133,11 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
     d.dim = S.dim;
     d.rot = S.rot;
     d.F = param_rows(S.dim - 3, S.rot).F;
+    d.prim_base = int64_t(n_prims);
+    n_prims += uint64_t(S.n);
+    n_grad_compact = n_grad_compact > uint64_t(d.F) * uint64_t(S.n) ? n_grad_compact
+                                                                       : uint64_t(d.F) * uint64_t(S.n);
+    if (n_prims > 0x7fffffffull) return UBS_ERR_UNSUPPORTED;
     ds->push_back(d);
   }
   uint64_t n_rec = 0, n_tiles = 0, n_pix = 0;
@@ -160,10 +186,11 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.n_passes = (l.pub.key_bits + tu.digit_bits - 1) / tu.digit_bits;
   const uint64_t cap = uint64_t(tu.pair_capacity);
   l.n_sort_blocks = int64_t((cap + kSortTile - 1) / kSortTile);
-  const uint64_t rec_scan_tiles = (n_rec + kScanTile - 1) / kScanTile;
-  const uint64_t hist_entries = uint64_t(1u << tu.digit_bits) * uint64_t(l.n_sort_blocks);
-  const uint64_t hist_scan_tiles = (hist_entries + kScanTile - 1) / kScanTile;
-  l.n_scan_blocks = int64_t(rec_scan_tiles > hist_scan_tiles ? rec_scan_tiles : hist_scan_tiles);
+  l.n_prims = int64_t(n_prims);
+  const uint64_t scan_n = n_rec > n_prims ? n_rec : n_prims;
+  const uint64_t rec_scan_tiles = (scan_n + kScanTile - 1) / kScanTile;
+  const uint64_t lookback_words = uint64_t(l.n_passes) * uint64_t(l.n_sort_blocks) * 256;
+  l.n_scan_blocks = int64_t(rec_scan_tiles);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) { const uint64_t o = off; off = align256(off + bytes); return o; };
   l.pub.off_status = take(sizeof(DevStatus));
@@ -171,17 +198,22 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.off_scenes = take(sizeof(DevScene) * uint64_t(f->n_scenes > 0 ? f->n_scenes : 1));
   l.pub.off_records = take(uint64_t(kRecFloats) * 4 * n_rec);
   l.off_counts = take(4 * n_rec);
-  l.off_offsets = take(4 * n_rec);
+  l.off_offsets = take(4 * scan_n);
   l.off_blocksums = take(4 * uint64_t(l.n_scan_blocks + 1));
   l.off_keys0 = take(8 * cap);
   l.off_keys_alt = take(8 * cap);
   l.off_values0 = take(4 * cap);
   l.off_values_alt = take(4 * cap);
-  l.off_hist = take(4 * hist_entries);
+  l.off_hist = take(4 * lookback_words);
+  l.off_sort_state = take(sizeof(SortState));
   l.pub.off_ranges = take(8 * n_tiles);
   l.pub.off_ncontrib = take(4 * n_pix);
   l.pub.off_grad2d = take(uint64_t(kGradFloats) * 4 * n_rec);
   l.off_tfinal_ws = take(4 * n_pix);
+  l.off_live = take(4 * n_prims);
+  l.off_live_list = take(4 * n_prims);
+  l.off_live_count = take(8 * uint64_t(f->n_scenes > 0 ? f->n_scenes : 1));
+  l.off_grad_compact = take(4 * n_grad_compact);
   l.pub.bytes = off;
   const bool odd = (l.n_passes & 1) != 0;
   l.pub.off_keys = odd ? l.off_keys_alt : l.off_keys0;
@@ -261,7 +293,8 @@ ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes, u
     bool used = false;
     for (const DevView& v : p.dv) used = used || v.scene == sc;
     if (!used) continue;
-    UBS_HIP(launch_preprocess_fwd(fp64, p.ds[sc], sc, views, frame->n_views, records, status, s));
+    UBS_HIP(launch_preprocess_fwd(fp64, p.ds[sc], sc, views, frame->n_views, records,
+                                  at<uint32_t>(ws, L.off_live) + p.ds[sc].prim_base, status, s));
   }
   stage_mark(frame, UBS_STAGE_PREPROCESS, 1, s);
   return UBS_OK;
@@ -289,14 +322,15 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
   UBS_HIP(launch_bin_count(records, views, frame->n_views, n_rec, counts, s));
   stage_mark(frame, UBS_STAGE_BIN_COUNT, 1, s);
   stage_mark(frame, UBS_STAGE_SCAN, 0, s);
-  UBS_HIP(launch_scan(counts, n_rec, sums, offsets, status, cap, s));
+  UBS_HIP(launch_scan(counts, n_rec, sums, offsets, status, cap, s, nullptr));
   stage_mark(frame, UBS_STAGE_SCAN, 1, s);
   stage_mark(frame, UBS_STAGE_BIN_EMIT, 0, s);
   UBS_HIP(launch_bin_emit(records, views, frame->n_views, n_rec, offsets, status, k0, v0, s));
   stage_mark(frame, UBS_STAGE_BIN_EMIT, 1, s);
   stage_mark(frame, UBS_STAGE_SORT, 0, s);
   UBS_HIP(launch_radix_sort(k0, v0, k1, v1, status, L.pub.key_bits, L.digit_bits,
-                            at<uint32_t>(ws, L.off_hist), sums, uint32_t(L.n_sort_blocks), s));
+                            at<SortState>(ws, L.off_sort_state), at<uint32_t>(ws, L.off_hist),
+                            uint32_t(L.n_sort_blocks), s));
   stage_mark(frame, UBS_STAGE_SORT, 1, s);
   stage_mark(frame, UBS_STAGE_RANGES, 0, s);
   UBS_HIP(launch_ranges(at<unsigned long long>(ws, L.pub.off_keys), status,
@@ -314,7 +348,9 @@ ubs_status ubs_render_fwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes, f
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Layout& L = p.L;
   stage_mark(frame, UBS_STAGE_RASTER_FWD, 0, s);
-  UBS_HIP(launch_raster_fwd(L.tile_w, L.tile_h, at<float>(ws, L.pub.off_records),
+  DevStatus* status = at<DevStatus>(ws, L.pub.off_status);
+  UBS_HIP(launch_raster_fwd(L.tile_w, L.tile_h, frame->tuning.batch_depth, persistent_blocks(frame),
+                            &status->work_counter[0], at<float>(ws, L.pub.off_records),
                             at<uint32_t>(ws, L.pub.off_values), at<uint32_t>(ws, L.pub.off_ranges),
                             at<DevView>(ws, L.off_views), frame->n_views, uint32_t(L.pub.n_tiles),
                             image, at<float>(ws, L.off_tfinal_ws), t_final,
@@ -349,7 +385,9 @@ ubs_status ubs_render_bwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
   const float l1_scale = L.pub.n_pixels > 0 ? float(1.0 / (3.0 * double(L.pub.n_pixels))) : 0.0f;
   const DevView* views = at<DevView>(ws, L.off_views);
   stage_mark(frame, UBS_STAGE_RASTER_BWD, 0, s);
-  UBS_HIP(launch_raster_bwd(L.tile_w, L.tile_h, at<float>(ws, L.pub.off_records),
+  DevStatus* status = at<DevStatus>(ws, L.pub.off_status);
+  UBS_HIP(launch_raster_bwd(L.tile_w, L.tile_h, frame->tuning.batch_depth, persistent_blocks(frame),
+                            &status->work_counter[1], at<float>(ws, L.pub.off_records),
                             at<uint32_t>(ws, L.pub.off_values), at<uint32_t>(ws, L.pub.off_ranges),
                             views, frame->n_views, uint32_t(L.pub.n_tiles),
                             at<float>(ws, L.off_tfinal_ws), at<uint32_t>(ws, L.pub.off_ncontrib),
@@ -369,8 +407,17 @@ ubs_status ubs_render_bwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
                          p.ds[sc].dparams, nf);
       continue;
     }
+    // compact the primitives some view kept; the adjoint runs only for those
+    const uint32_t* live = at<uint32_t>(ws, L.off_live) + p.ds[sc].prim_base;
+    uint32_t* list = at<uint32_t>(ws, L.off_live_list) + p.ds[sc].prim_base;
+    unsigned long long* n_live = at<unsigned long long>(ws, L.off_live_count) + sc;
+    uint32_t* offs = at<uint32_t>(ws, L.off_offsets);
+    UBS_HIP(launch_scan(live, uint32_t(p.ds[sc].n), at<uint32_t>(ws, L.off_blocksums), offs,
+                        nullptr, 0ull, s, n_live));
+    UBS_HIP(launch_compact(live, offs, uint32_t(p.ds[sc].n), list, s));
     UBS_HIP(launch_preprocess_bwd(fp64, p.ds[sc], sc, views, frame->n_views,
-                                  at<float>(ws, L.pub.off_records), grad2d, s));
+                                  at<float>(ws, L.pub.off_records), grad2d, live, offs, list,
+                                  n_live, at<float>(ws, L.off_grad_compact), s));
   }
   stage_mark(frame, UBS_STAGE_PRE_BWD, 1, s);
   UBS_HIP(hipGetLastError());

@@ -94,20 +94,94 @@ __device__ __forceinline__ bool record_hits_tile(const float4 r0, const float4 r
                             double(py1) + 0.5);
 }
 
+// Records whose conservative tile box holds more than kSmallBox candidates are
+// binned by the whole wavefront (lanes take consecutive candidates in
+// row-major order); smaller ones by their own lane.
+constexpr int kSmallBox = 16;
+
+struct BinRec {
+  float4 r0, r1;
+  float depth;
+  int view;
+  TileBox box;
+  int n_cand;
+};
+
+__device__ __forceinline__ int bcast_i(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+__device__ __forceinline__ float bcast_f(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
+__device__ __forceinline__ BinRec bcast_rec(const BinRec& b, int src) {
+  BinRec o;
+  o.r0 = make_float4(bcast_f(b.r0.x, src), bcast_f(b.r0.y, src), bcast_f(b.r0.z, src), bcast_f(b.r0.w, src));
+  o.r1 = make_float4(bcast_f(b.r1.x, src), bcast_f(b.r1.y, src), bcast_f(b.r1.z, src), bcast_f(b.r1.w, src));
+  o.depth = bcast_f(b.depth, src);
+  o.view = bcast_i(b.view, src);
+  o.box.tx0 = bcast_i(b.box.tx0, src);
+  o.box.tx1 = bcast_i(b.box.tx1, src);
+  o.box.ty0 = bcast_i(b.box.ty0, src);
+  o.box.ty1 = bcast_i(b.box.ty1, src);
+  o.n_cand = bcast_i(b.n_cand, src);
+  return o;
+}
+
+__device__ __forceinline__ BinRec load_bin_rec(const float* __restrict__ records,
+                                               const DevView* __restrict__ views, int n_views,
+                                               uint32_t rec, bool active) {
+  BinRec b;
+  b.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+  b.r1 = b.r0;
+  b.depth = 0.f;
+  b.view = 0;
+  b.box = TileBox{1, 0, 1, 0};
+  b.n_cand = 0;
+  if (active) {
+    const float4* rp = reinterpret_cast<const float4*>(records + size_t(rec) * kRecFloats);
+    b.r0 = rp[0];
+    b.r1 = rp[1];
+    b.depth = records[size_t(rec) * kRecFloats + 11];
+    b.view = view_of_record(views, n_views, rec);
+    b.box = record_tile_box(b.r0, b.r1, views[b.view]);
+    if (b.box.tx0 <= b.box.tx1 && b.box.ty0 <= b.box.ty1)
+      b.n_cand = (b.box.tx1 - b.box.tx0 + 1) * (b.box.ty1 - b.box.ty0 + 1);
+  }
+  return b;
+}
+
 __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict__ records,
                                                         const DevView* __restrict__ views,
                                                         int n_views, uint32_t n_records,
                                                         uint32_t* __restrict__ counts) {
   const uint32_t rec = blockIdx.x * 256u + threadIdx.x;
-  if (rec >= n_records) return;
-  const float4* rp = reinterpret_cast<const float4*>(records + size_t(rec) * kRecFloats);
-  const float4 r0 = rp[0], r1 = rp[1];
-  const DevView& V = views[view_of_record(views, n_views, rec)];
-  const TileBox bx = record_tile_box(r0, r1, V);
+  const bool active = rec < n_records;
+  const int lane = threadIdx.x & 63;
+  const BinRec b = load_bin_rec(records, views, n_views, rec, active);
   uint32_t cnt = 0;
-  for (int ty = bx.ty0; ty <= bx.ty1; ++ty)
-    for (int tx = bx.tx0; tx <= bx.tx1; ++tx) cnt += record_hits_tile(r0, r1, V, tx, ty) ? 1u : 0u;
-  counts[rec] = cnt;
+  if (b.n_cand > 0 && b.n_cand <= kSmallBox) {
+    const DevView& V = views[b.view];
+    for (int ty = b.box.ty0; ty <= b.box.ty1; ++ty)
+      for (int tx = b.box.tx0; tx <= b.box.tx1; ++tx)
+        cnt += record_hits_tile(b.r0, b.r1, V, tx, ty) ? 1u : 0u;
+  }
+  unsigned long long big = __ballot(b.n_cand > kSmallBox);
+  while (big) {
+    const int src = __ffsll((long long)big) - 1;
+    big &= big - 1ull;
+    const BinRec o = bcast_rec(b, src);
+    const DevView& V = views[o.view];
+    const int bw = o.box.tx1 - o.box.tx0 + 1;
+    uint32_t total = 0;
+    for (int c0 = 0; c0 < o.n_cand; c0 += 64) {
+      const int c = c0 + lane;
+      bool hit = false;
+      if (c < o.n_cand)
+        hit = record_hits_tile(o.r0, o.r1, V, o.box.tx0 + c % bw, o.box.ty0 + c / bw);
+      total += uint32_t(__popcll(__ballot(hit)));
+    }
+    if (lane == src) cnt = total;
+  }
+  if (active) counts[rec] = cnt;
 }
 
 __global__ void __launch_bounds__(256) bin_emit_kernel(const float* __restrict__ records,
@@ -117,26 +191,54 @@ __global__ void __launch_bounds__(256) bin_emit_kernel(const float* __restrict__
                                                        const DevStatus* __restrict__ status,
                                                        unsigned long long* __restrict__ keys,
                                                        uint32_t* __restrict__ values) {
-  const uint32_t rec = blockIdx.x * 256u + threadIdx.x;
-  if (rec >= n_records) return;
   if (status->overflow) return;
-  const float4* rp = reinterpret_cast<const float4*>(records + size_t(rec) * kRecFloats);
-  const float4 r0 = rp[0], r1 = rp[1];
-  const float depth = records[size_t(rec) * kRecFloats + 11];
-  const DevView& V = views[view_of_record(views, n_views, rec)];
-  const TileBox bx = record_tile_box(r0, r1, V);
-  uint32_t pos = offsets[rec];
-  const unsigned long long dbits = __float_as_uint(depth);
-  for (int ty = bx.ty0; ty <= bx.ty1; ++ty)
-    for (int tx = bx.tx0; tx <= bx.tx1; ++tx) {
-      if (record_hits_tile(r0, r1, V, tx, ty)) {
+  const uint32_t rec = blockIdx.x * 256u + threadIdx.x;
+  const bool active = rec < n_records;
+  const int lane = threadIdx.x & 63;
+  const BinRec b = load_bin_rec(records, views, n_views, rec, active);
+  const uint32_t my_off = active ? offsets[rec] : 0u;
+  if (b.n_cand > 0 && b.n_cand <= kSmallBox) {
+    const DevView& V = views[b.view];
+    const unsigned long long dbits = __float_as_uint(b.depth);
+    uint32_t pos = my_off;
+    for (int ty = b.box.ty0; ty <= b.box.ty1; ++ty)
+      for (int tx = b.box.tx0; tx <= b.box.tx1; ++tx) {
+        if (record_hits_tile(b.r0, b.r1, V, tx, ty)) {
+          const unsigned long long tile =
+              (unsigned long long)V.tile_base + (unsigned long long)(ty * V.tiles_x + tx);
+          keys[pos] = (tile << 32) | dbits;
+          values[pos] = rec;
+          ++pos;
+        }
+      }
+  }
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  unsigned long long big = __ballot(b.n_cand > kSmallBox);
+  while (big) {
+    const int src = __ffsll((long long)big) - 1;
+    big &= big - 1ull;
+    const BinRec o = bcast_rec(b, src);
+    const uint32_t orec = uint32_t(bcast_i(int(rec), src));
+    uint32_t pos = uint32_t(bcast_i(int(my_off), src));
+    const DevView& V = views[o.view];
+    const unsigned long long dbits = __float_as_uint(o.depth);
+    const int bw = o.box.tx1 - o.box.tx0 + 1;
+    for (int c0 = 0; c0 < o.n_cand; c0 += 64) {
+      const int c = c0 + lane;
+      const int tx = o.box.tx0 + c % bw, ty = o.box.ty0 + c / bw;
+      bool hit = false;
+      if (c < o.n_cand) hit = record_hits_tile(o.r0, o.r1, V, tx, ty);
+      const unsigned long long m = __ballot(hit);
+      if (hit) {
+        const uint32_t p = pos + uint32_t(__popcll(m & lt_mask));
         const unsigned long long tile =
             (unsigned long long)V.tile_base + (unsigned long long)(ty * V.tiles_x + tx);
-        keys[pos] = (tile << 32) | dbits;
-        values[pos] = rec;
-        ++pos;
+        keys[p] = (tile << 32) | dbits;
+        values[p] = orec;
       }
+      pos += uint32_t(__popcll(m));
     }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -180,10 +282,11 @@ __global__ void __launch_bounds__(kScanThreads) scan_tile_sums_kernel(
   if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
 }
 
-// One block scans all tile sums in place (exclusive) and writes the total.
+// One block scans all tile sums in place (exclusive) and writes the total
+// (and, for the pair scan, the overflow flag of the status block).
 __global__ void __launch_bounds__(kScanThreads) scan_tile_sums_scan_kernel(
     uint32_t* __restrict__ tile_sums, uint32_t n_tiles, DevStatus* __restrict__ status,
-    unsigned long long capacity) {
+    unsigned long long capacity, unsigned long long* __restrict__ total_out) {
   __shared__ uint32_t lds[8];
   unsigned long long carry = 0;
   for (uint32_t base = 0; base < n_tiles; base += kScanThreads) {
@@ -198,6 +301,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_tile_sums_scan_kernel(
     status->pairs_needed = carry;
     status->overflow = carry > capacity ? 1u : 0u;
   }
+  if (threadIdx.x == 0 && total_out != nullptr) *total_out = carry;
 }
 
 __global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(
@@ -253,13 +357,14 @@ hipError_t launch_bin_count(const float* records, const DevView* views, int n_vi
 }
 
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
-                       DevStatus* status, unsigned long long capacity, hipStream_t st) {
+                       DevStatus* status, unsigned long long capacity, hipStream_t st,
+                       unsigned long long* total_out) {
   const uint32_t n_tiles = (n + kScanTile - 1) / kScanTile;
   if (n_tiles > 0)
     hipLaunchKernelGGL(scan_tile_sums_kernel, dim3(n_tiles), dim3(kScanThreads), 0, st, in, n,
                        tile_sums);
   hipLaunchKernelGGL(scan_tile_sums_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, tile_sums,
-                     n_tiles, status, capacity);
+                     n_tiles, status, capacity, total_out);
   if (n_tiles > 0)
     hipLaunchKernelGGL(scan_apply_kernel, dim3(n_tiles), dim3(kScanThreads), 0, st, in, n,
                        tile_sums, out);
@@ -272,6 +377,21 @@ hipError_t launch_bin_emit(const float* records, const DevView* views, int n_vie
   if (n_records == 0) return hipSuccess;
   hipLaunchKernelGGL(bin_emit_kernel, dim3((n_records + 255) / 256), dim3(256), 0, st, records,
                      views, n_views, n_records, offsets, status, keys, values);
+  return hipGetLastError();
+}
+
+// Compacted list of the set entries of a 0/1 flag array, given its exclusive scan.
+__global__ void __launch_bounds__(256) compact_kernel(const uint32_t* __restrict__ flags,
+                                                      const uint32_t* __restrict__ offsets,
+                                                      uint32_t n, uint32_t* __restrict__ list) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i < n && flags[i]) list[offsets[i]] = i;
+}
+
+hipError_t launch_compact(const uint32_t* flags, const uint32_t* offsets, uint32_t n,
+                          uint32_t* list, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(compact_kernel, dim3((n + 255) / 256), dim3(256), 0, st, flags, offsets, n, list);
   return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@ template <typename T, int C, int ROT>
 __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int scene,
                                                              const DevView* __restrict__ views,
                                                              int n_views, float* __restrict__ records,
+                                                             uint32_t* __restrict__ live,
                                                              DevStatus* __restrict__ status) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   const bool active = i < S.n;
@@ -55,26 +56,43 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
     rp[1] = o1;
     rp[2] = o2;
   }
-  // wavefront-aggregated counters
+  if (active) live[i] = visible > 0 ? 1u : 0u;
+  // workgroup-aggregated counters: one atomic per workgroup and counter (the
+  // status words are single addresses every workgroup updates)
+  __shared__ uint32_t s_cnt[2];
+  if (threadIdx.x == 0) { s_cnt[0] = 0; s_cnt[1] = 0; }
+  __syncthreads();
   const unsigned long long nf = __ballot(active && !finite);
   const int lane = threadIdx.x & 63;
   uint32_t vis = visible;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) vis += __shfl_xor(vis, o, 64);
   if (lane == 0) {
-    if (nf) atomicAdd(&status->n_nonfinite, uint32_t(__popcll(nf)));
-    if (vis) atomicAdd(&status->n_visible, vis);
+    if (nf) atomicAdd(&s_cnt[0], uint32_t(__popcll(nf)));
+    if (vis) atomicAdd(&s_cnt[1], vis);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_cnt[0]) atomicAdd(&status->n_nonfinite, s_cnt[0]);
+    if (s_cnt[1]) atomicAdd(&status->n_visible, s_cnt[1]);
   }
 }
 
+// Thread t runs the adjoint of the t-th live primitive of the compacted list
+// and writes its gradient to column t of the compacted [F][n] buffer
+// (coalesced); scatter_dparams_kernel moves it to the primitive's column.
 template <typename T, int C, int ROT>
 __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int scene,
                                                              const DevView* __restrict__ views,
                                                              int n_views,
                                                              const float* __restrict__ records,
-                                                             const float* __restrict__ grad2d) {
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (i >= S.n) return;
+                                                             const float* __restrict__ grad2d,
+                                                             const uint32_t* __restrict__ list,
+                                                             const unsigned long long* __restrict__ n_live,
+                                                             float* __restrict__ compact) {
+  const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (t >= int64_t(*n_live)) return;
+  const int64_t i = list[t];
   Raw<C, ROT> r;
   load_raw<C, ROT>(S.params, S.n, i, r);
   Geo<T, C, ROT> g;
@@ -99,72 +117,93 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int sce
   float out[64];
   geo_backward<T, C, ROT>(r, g, G, out);
 #pragma unroll
-  for (int k = 0; k < pr.F; ++k) S.dparams[int64_t(k) * S.n + i] = out[k];
+  for (int k = 0; k < pr.F; ++k) compact[int64_t(k) * S.n + t] = out[k];
+}
+
+// dparams[:, i] = compact[:, offs[i]] for live primitives, 0 otherwise.
+__global__ void __launch_bounds__(256) scatter_dparams_kernel(DevScene S,
+                                                              const uint32_t* __restrict__ live,
+                                                              const uint32_t* __restrict__ offs,
+                                                              const float* __restrict__ compact) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= S.n) return;
+  const bool is_live = live[i] != 0;
+  const int64_t j = is_live ? int64_t(offs[i]) : 0;
+  for (int k = 0; k < S.F; ++k)
+    S.dparams[int64_t(k) * S.n + i] = is_live ? compact[int64_t(k) * S.n + j] : 0.0f;
 }
 
 template <typename T, int C, int ROT>
 static hipError_t pre_fwd_t(const DevScene& S, int scene, const DevView* views, int n_views,
-                            float* records, DevStatus* status, hipStream_t st) {
+                            float* records, uint32_t* live, DevStatus* status, hipStream_t st) {
   const unsigned blocks = unsigned((S.n + 255) / 256);
   hipLaunchKernelGGL((preprocess_fwd_kernel<T, C, ROT>), dim3(blocks), dim3(256), 0, st, S, scene,
-                     views, n_views, records, status);
+                     views, n_views, records, live, status);
   return hipGetLastError();
 }
 
 template <typename T, int C, int ROT>
 static hipError_t pre_bwd_t(const DevScene& S, int scene, const DevView* views, int n_views,
-                            const float* records, const float* grad2d, hipStream_t st) {
+                            const float* records, const float* grad2d, const uint32_t* live,
+                            const uint32_t* offs, const uint32_t* list,
+                            const unsigned long long* n_live, float* compact, hipStream_t st) {
   const unsigned blocks = unsigned((S.n + 255) / 256);
   hipLaunchKernelGGL((preprocess_bwd_kernel<T, C, ROT>), dim3(blocks), dim3(256), 0, st, S, scene,
-                     views, n_views, records, grad2d);
+                     views, n_views, records, grad2d, list, n_live, compact);
+  hipLaunchKernelGGL(scatter_dparams_kernel, dim3(blocks), dim3(256), 0, st, S, live, offs, compact);
   return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t pre_fwd_dispatch(const DevScene& S, int scene, const DevView* views, int n_views,
-                                   float* records, DevStatus* status, hipStream_t st) {
+                                   float* records, uint32_t* live, DevStatus* status, hipStream_t st) {
   const int C = S.dim - 3;
   if (S.rot == UBS_ROT_QUAT) {
-    if (C == 0) return pre_fwd_t<T, 0, 0>(S, scene, views, n_views, records, status, st);
-    if (C == 3) return pre_fwd_t<T, 3, 0>(S, scene, views, n_views, records, status, st);
-    if (C == 4) return pre_fwd_t<T, 4, 0>(S, scene, views, n_views, records, status, st);
+    if (C == 0) return pre_fwd_t<T, 0, 0>(S, scene, views, n_views, records, live, status, st);
+    if (C == 3) return pre_fwd_t<T, 3, 0>(S, scene, views, n_views, records, live, status, st);
+    if (C == 4) return pre_fwd_t<T, 4, 0>(S, scene, views, n_views, records, live, status, st);
   } else {
-    if (C == 0) return pre_fwd_t<T, 0, 1>(S, scene, views, n_views, records, status, st);
-    if (C == 3) return pre_fwd_t<T, 3, 1>(S, scene, views, n_views, records, status, st);
-    if (C == 4) return pre_fwd_t<T, 4, 1>(S, scene, views, n_views, records, status, st);
+    if (C == 0) return pre_fwd_t<T, 0, 1>(S, scene, views, n_views, records, live, status, st);
+    if (C == 3) return pre_fwd_t<T, 3, 1>(S, scene, views, n_views, records, live, status, st);
+    if (C == 4) return pre_fwd_t<T, 4, 1>(S, scene, views, n_views, records, live, status, st);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename T>
 static hipError_t pre_bwd_dispatch(const DevScene& S, int scene, const DevView* views, int n_views,
-                                   const float* records, const float* grad2d, hipStream_t st) {
+                                   const float* records, const float* grad2d, const uint32_t* live,
+                                   const uint32_t* offs, const uint32_t* list,
+                                   const unsigned long long* n_live, float* compact,
+                                   hipStream_t st) {
   const int C = S.dim - 3;
   if (S.rot == UBS_ROT_QUAT) {
-    if (C == 0) return pre_bwd_t<T, 0, 0>(S, scene, views, n_views, records, grad2d, st);
-    if (C == 3) return pre_bwd_t<T, 3, 0>(S, scene, views, n_views, records, grad2d, st);
-    if (C == 4) return pre_bwd_t<T, 4, 0>(S, scene, views, n_views, records, grad2d, st);
+    if (C == 0) return pre_bwd_t<T, 0, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
+    if (C == 3) return pre_bwd_t<T, 3, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
+    if (C == 4) return pre_bwd_t<T, 4, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
   } else {
-    if (C == 0) return pre_bwd_t<T, 0, 1>(S, scene, views, n_views, records, grad2d, st);
-    if (C == 3) return pre_bwd_t<T, 3, 1>(S, scene, views, n_views, records, grad2d, st);
-    if (C == 4) return pre_bwd_t<T, 4, 1>(S, scene, views, n_views, records, grad2d, st);
+    if (C == 0) return pre_bwd_t<T, 0, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
+    if (C == 3) return pre_bwd_t<T, 3, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
+    if (C == 4) return pre_bwd_t<T, 4, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_preprocess_fwd(bool fp64, const DevScene& S, int scene, const DevView* views,
-                                 int n_views, float* records, DevStatus* status, hipStream_t st) {
+                                 int n_views, float* records, uint32_t* live, DevStatus* status,
+                                 hipStream_t st) {
   if (S.n == 0) return hipSuccess;
-  return fp64 ? pre_fwd_dispatch<double>(S, scene, views, n_views, records, status, st)
-              : pre_fwd_dispatch<float>(S, scene, views, n_views, records, status, st);
+  return fp64 ? pre_fwd_dispatch<double>(S, scene, views, n_views, records, live, status, st)
+              : pre_fwd_dispatch<float>(S, scene, views, n_views, records, live, status, st);
 }
 
 hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const DevView* views,
                                  int n_views, const float* records, const float* grad2d,
-                                 hipStream_t st) {
+                                 const uint32_t* live, const uint32_t* offs, const uint32_t* list,
+                                 const unsigned long long* n_live, float* compact, hipStream_t st) {
   if (S.n == 0) return hipSuccess;
-  return fp64 ? pre_bwd_dispatch<double>(S, scene, views, n_views, records, grad2d, st)
-              : pre_bwd_dispatch<float>(S, scene, views, n_views, records, grad2d, st);
+  return fp64 ? pre_bwd_dispatch<double>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st)
+              : pre_bwd_dispatch<float>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
 }
 
 }  // namespace ubs

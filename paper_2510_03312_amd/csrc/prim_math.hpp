@@ -96,61 +96,68 @@ __device__ __forceinline__ void load_raw(const float* __restrict__ P, int64_t n,
 // View-independent quantities of a primitive.
 template <typename T, int C, int ROT>
 struct Geo {
-  T R[3][3];
   T s[3];
   T M[3][3];                         // R diag(s)
   T Sx[3][3];
   T Sxq[3][Cdim<C>::V];
-  T Lq[Cdim<C>::V][Cdim<C>::V];      // activated L_q (lower)
   T Lh[Cdim<C>::V][Cdim<C>::V];      // chol(Sigma_q)
   T Li[Cdim<C>::V][Cdim<C>::V];      // Lh^-1 (lower)
-  T K[3][Cdim<C>::V];                // Sigma_xq Sigma_q^-1
   T bt[Cdim<C>::V];                  // min(exp(b_q), 1)
   T e[Cdim<C>::V];                   // 4 exp(b_q)
   bool ok;
 };
 
+// Activated L_q (lower triangular, diagonal exp of the stored log scale).
+template <typename T, int C, int ROT>
+__device__ __forceinline__ T lq_entry(const Raw<C, ROT>& r, int a, int b) {
+  return b < a ? T(r.lq[a][b]) : (b == a ? m_exp<T>(T(r.lq[a][a])) : T(0));
+}
+
 template <typename T, int C, int ROT>
 __device__ __forceinline__ void geo_forward(const Raw<C, ROT>& r, Geo<T, C, ROT>& g) {
   g.ok = r.finite;
+  struct { T R[3][3]; } gr;
+  auto& R = gr.R;
   if (ROT == UBS_ROT_QUAT) {
     T w = r.rq[0], x = r.rq[1], y = r.rq[2], z = r.rq[3];
     T nn = w * w + x * x + y * y + z * z;
     T inv = T(1) / m_sqrt<T>(nn);
     if (!(nn > T(0))) g.ok = false;
     w *= inv; x *= inv; y *= inv; z *= inv;
-    g.R[0][0] = T(1) - T(2) * (y * y + z * z);
-    g.R[0][1] = T(2) * (x * y - w * z);
-    g.R[0][2] = T(2) * (x * z + w * y);
-    g.R[1][0] = T(2) * (x * y + w * z);
-    g.R[1][1] = T(1) - T(2) * (x * x + z * z);
-    g.R[1][2] = T(2) * (y * z - w * x);
-    g.R[2][0] = T(2) * (x * z - w * y);
-    g.R[2][1] = T(2) * (y * z + w * x);
-    g.R[2][2] = T(1) - T(2) * (x * x + y * y);
+    R[0][0] = T(1) - T(2) * (y * y + z * z);
+    R[0][1] = T(2) * (x * y - w * z);
+    R[0][2] = T(2) * (x * z + w * y);
+    R[1][0] = T(2) * (x * y + w * z);
+    R[1][1] = T(1) - T(2) * (x * x + z * z);
+    R[1][2] = T(2) * (y * z - w * x);
+    R[2][0] = T(2) * (x * z - w * y);
+    R[2][1] = T(2) * (y * z + w * x);
+    R[2][2] = T(1) - T(2) * (x * x + y * y);
   } else {
     T w1 = r.rq[0], w2 = r.rq[1], w3 = r.rq[2];
-    g.R[0][0] = T(1); g.R[0][1] = -w3;  g.R[0][2] = w2;
-    g.R[1][0] = w3;   g.R[1][1] = T(1); g.R[1][2] = -w1;
-    g.R[2][0] = -w2;  g.R[2][1] = w1;   g.R[2][2] = T(1);
+    R[0][0] = T(1); R[0][1] = -w3;  R[0][2] = w2;
+    R[1][0] = w3;   R[1][1] = T(1); R[1][2] = -w1;
+    R[2][0] = -w2;  R[2][1] = w1;   R[2][2] = T(1);
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) g.s[k] = m_exp<T>(T(r.logs[k]));
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) g.M[a][b] = g.R[a][b] * g.s[b];
+    for (int b = 0; b < 3; ++b) g.M[a][b] = R[a][b] * g.s[b];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b)
+    for (int b = 0; b <= a; ++b) {
       g.Sx[a][b] = g.M[a][0] * g.M[b][0] + g.M[a][1] * g.M[b][1] + g.M[a][2] * g.M[b][2];
+      g.Sx[b][a] = g.Sx[a][b];
+    }
   if constexpr (C > 0) {
+    T Lq[Cdim<C>::V][Cdim<C>::V];
 #pragma unroll
     for (int a = 0; a < C; ++a)
 #pragma unroll
-      for (int b = 0; b < C; ++b)
-        g.Lq[a][b] = b < a ? T(r.lq[a][b]) : (b == a ? m_exp<T>(T(r.lq[a][a])) : T(0));
+      for (int b = 0; b < C; ++b) Lq[a][b] = lq_entry<T, C, ROT>(r, a, b);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -164,7 +171,7 @@ __device__ __forceinline__ void geo_forward(const Raw<C, ROT>& r, Geo<T, C, ROT>
         T acc = T(r.lqx[a][0]) * T(r.lqx[b][0]) + T(r.lqx[a][1]) * T(r.lqx[b][1]) +
                 T(r.lqx[a][2]) * T(r.lqx[b][2]);
 #pragma unroll
-        for (int k = 0; k < C; ++k) acc += g.Lq[a][k] * g.Lq[b][k];
+        for (int k = 0; k < C; ++k) acc += Lq[a][k] * Lq[b][k];
         Sq[a][b] = acc;
       }
     // Cholesky of Sigma_q (lower, positive diagonal)
@@ -198,25 +205,6 @@ __device__ __forceinline__ void geo_forward(const Raw<C, ROT>& r, Geo<T, C, ROT>
 #pragma unroll
         for (int k = j; k < i; ++k) acc += g.Lh[i][k] * g.Li[k][j];
         g.Li[i][j] = -acc / g.Lh[i][i];
-      }
-    }
-    // K = Sigma_xq Lh^-T Lh^-1
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      T A[Cdim<C>::V];
-#pragma unroll
-      for (int k = 0; k < C; ++k) {   // A = Sigma_xq Li^T
-        T acc = T(0);
-#pragma unroll
-        for (int m = 0; m <= k; ++m) acc += g.Sxq[a][m] * g.Li[k][m];
-        A[k] = acc;
-      }
-#pragma unroll
-      for (int k = 0; k < C; ++k) {   // K = A Li
-        T acc = T(0);
-#pragma unroll
-        for (int m = k; m < C; ++m) acc += A[m] * g.Li[m][k];
-        g.K[a][k] = acc;
       }
     }
 #pragma unroll
@@ -291,7 +279,26 @@ __device__ __forceinline__ void view_forward(const Raw<C, ROT>& r, const Geo<T, 
       lsum += g.e[i] * s.ell[i];
     }
     oq = T(r.o) * m_exp<T>(lsum);
-    // conditioning
+    // conditioning: K = Sigma_xq Sigma_q^-1 = (Sigma_xq Lh^-T) Lh^-1
+    T K[3][Cdim<C>::V];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      T A[Cdim<C>::V];
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m <= k; ++m) acc += g.Sxq[a][m] * g.Li[k][m];
+        A[k] = acc;
+      }
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        T acc = T(0);
+#pragma unroll
+        for (int m = k; m < C; ++m) acc += A[m] * g.Li[m][k];
+        K[a][k] = acc;
+      }
+    }
     T Dv[Cdim<C>::V];
 #pragma unroll
     for (int k = 0; k < C; ++k) Dv[k] = g.bt[k] * s.v[k];
@@ -299,7 +306,7 @@ __device__ __forceinline__ void view_forward(const Raw<C, ROT>& r, const Geo<T, 
     for (int a = 0; a < 3; ++a) {
       T acc = T(0);
 #pragma unroll
-      for (int k = 0; k < C; ++k) acc += g.K[a][k] * Dv[k];
+      for (int k = 0; k < C; ++k) acc += K[a][k] * Dv[k];
       mu_c[a] += acc;
     }
     T X[3][3];   // K diag(bt) Sigma_qx
@@ -309,7 +316,7 @@ __device__ __forceinline__ void view_forward(const Raw<C, ROT>& r, const Geo<T, 
       for (int b = 0; b < 3; ++b) {
         T acc = T(0);
 #pragma unroll
-        for (int k = 0; k < C; ++k) acc += g.K[a][k] * g.bt[k] * g.Sxq[b][k];
+        for (int k = 0; k < C; ++k) acc += K[a][k] * g.bt[k] * g.Sxq[b][k];
         X[a][b] = acc;
       }
 #pragma unroll
@@ -367,15 +374,16 @@ __device__ __forceinline__ void view_forward(const Raw<C, ROT>& r, const Geo<T, 
   s.live = live;
 }
 
-// Gradients w.r.t. the view-independent quantities, summed over views.
+// Gradients w.r.t. the view-independent quantities, summed over views
+// (accumulated in float32: each view's contribution is evaluated in T).
 template <typename T, int C>
 struct GeoGrad {
-  T Sx[3][3];
-  T Sxq[3][Cdim<C>::V];
-  T Z[Cdim<C>::V][Cdim<C>::V];   // w.r.t. Sigma_q^-1 (symmetric part used)
-  T Lh[Cdim<C>::V][Cdim<C>::V];  // w.r.t. chol(Sigma_q) (lower)
-  T mu[3], muq[Cdim<C>::V], bq[Cdim<C>::V], bt[Cdim<C>::V];
-  T bx, o, rgb[3];
+  float Sx[3][3];
+  float Sxq[3][Cdim<C>::V];
+  float Z[Cdim<C>::V][Cdim<C>::V];   // w.r.t. Sigma_q^-1 (symmetric part used)
+  float Lh[Cdim<C>::V][Cdim<C>::V];  // w.r.t. chol(Sigma_q) (lower)
+  float mu[3], muq[Cdim<C>::V], bq[Cdim<C>::V], bt[Cdim<C>::V];
+  float bx, o, rgb[3];
 };
 
 template <typename T, int C>
@@ -688,8 +696,8 @@ __device__ __forceinline__ void geo_backward(const Raw<C, ROT>& r, const Geo<T, 
       for (int j = 0; j <= i; ++j) {
         T acc = T(0);
 #pragma unroll
-        for (int m = 0; m < C; ++m) acc += GSs[i][m] * g.Lq[m][j];
-        out[pr.lq + idx] = float(i == j ? acc * g.Lq[i][i] : acc);
+        for (int m = j; m < C; ++m) acc += GSs[i][m] * lq_entry<T, C, ROT>(r, m, j);
+        out[pr.lq + idx] = float(i == j ? acc * lq_entry<T, C, ROT>(r, i, i) : acc);
         ++idx;
       }
 #pragma unroll
@@ -717,9 +725,9 @@ __device__ __forceinline__ void geo_backward(const Raw<C, ROT>& r, const Geo<T, 
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       GR[i][j] = GM[i][j] * g.s[j];
-      acc += GM[i][j] * g.R[i][j];
+      acc += GM[i][j] * g.M[i][j];   // M = R diag(s): d/d log s_j = sum_i GM_ij R_ij s_j
     }
-    out[pr.log_s + j] = float(acc * g.s[j]);
+    out[pr.log_s + j] = float(acc);
   }
   if (ROT == UBS_ROT_QUAT) {
     T qn = m_sqrt<T>(T(r.rq[0]) * T(r.rq[0]) + T(r.rq[1]) * T(r.rq[1]) + T(r.rq[2]) * T(r.rq[2]) +

@@ -1,13 +1,20 @@
 // Per-tile rasterisation: front-to-back compositing and its adjoint.
 //
-// One workgroup per tile, one lane per pixel.  The tile's sorted records are
-// staged through LDS in batches (one record per lane per batch); every lane
-// then walks the batch.  The forward pass stops a pixel before the first
-// record that would take its transmittance below 1e-4, and the workgroup
-// stops when all its pixels have stopped.  The backward pass walks each
-// tile back to front from the last contributor, recovers the transmittance
-// in front of each record by division, reduces the per-record gradients
-// over each wavefront and accumulates them with one atomic per component.
+// One wavefront (64 lanes) per tile.  Lane l owns the pixels of column
+// l % TW in rows l / TW + k * (64 / TW), k < TW * TH / 64 (a 16x16 tile gives
+// each lane a strip of 4 pixels).  The tile's sorted records are staged
+// through LDS 64 at a time (one per lane); every lane then walks the batch.
+// Because a lane's pixels share one column, dx = px - mx is shared and the
+// quadratic form costs r = A + dy (B + c dy) per pixel with A, B per record.
+//
+// Forward: a pixel stops before the first record that would take its
+// transmittance below 1e-4; the wavefront stops when all its pixels have.
+// Backward: each tile is walked back to front from the last contributor;
+// the transmittance in front of a record is recovered by division.  A lane
+// first sums the gradient terms of its own pixels, the wavefront then sums
+// over each 16-lane row with a DPP scan, passes the four row totals through
+// LDS, and lanes 0..9 add the ten per-record totals to the record's
+// accumulator with one atomic each.
 //
 // Both passes take every per-pixel decision (support test, skip, stop)
 // through the same inline functions, so the backward pass visits exactly
@@ -37,9 +44,16 @@ __device__ __forceinline__ Staged stage_record(const float* __restrict__ records
   return s;
 }
 
-// r = a dx^2 + 2 b dx dy + c dy^2 (squared Mahalanobis distance).
-__device__ __forceinline__ float eval_r(const float4 g0, float c, float dx, float dy) {
-  return dx * (g0.z * dx + g0.w * dy) + c * dy * dy;
+// Column terms of the quadratic form for one record and one lane:
+// r = a dx^2 + 2 b dx dy + c dy^2 = A + dy (B + c dy), A = dx (a dx), B = 2b dx.
+struct ColTerms {
+  float A, B;
+};
+__device__ __forceinline__ ColTerms col_terms(const float4 g0, float dx) {
+  return ColTerms{dx * (g0.z * dx), g0.w * dx};
+}
+__device__ __forceinline__ float eval_r(const ColTerms t, float c, float dy) {
+  return t.A + dy * (t.B + c * dy);
 }
 
 // sigma = o (1 - r)^beta = exp2(log2 o + beta log2(1 - r)); alpha = min(0.99, sigma).
@@ -60,246 +74,395 @@ __device__ __forceinline__ int view_of_tile(const DevView* __restrict__ views, i
 }
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH) raster_fwd_kernel(
-    const float* __restrict__ records, const uint32_t* __restrict__ values,
-    const uint32_t* __restrict__ ranges, const DevView* __restrict__ views, int n_views,
-    float* __restrict__ image, float* __restrict__ t_ws, float* __restrict__ t_user,
-    uint32_t* __restrict__ ncontrib) {
-  constexpr int NT = TW * TH;
-  __shared__ float4 s0[NT], s1[NT], s2[NT];
-  const uint32_t tile = blockIdx.x;
-  const int vi = view_of_tile(views, n_views, tile);
-  const DevView& V = views[vi];
+struct TileGeom {
+  static constexpr int PPL = TW * TH / 64;   // pixels per lane
+  static constexpr int RSTEP = 64 / TW;      // rows between a lane's pixels
+  static_assert(TW * TH % 64 == 0 && 64 % TW == 0, "tile shape");
+};
+
+template <int TW, int TH, int BATCH>
+__device__ __forceinline__ void raster_fwd_tile(
+    uint32_t tile, float4* s0, float4* s1, float4* s2, const float* __restrict__ records,
+    const uint32_t* __restrict__ values, const uint32_t* __restrict__ ranges,
+    const DevView* __restrict__ views, int n_views, float* __restrict__ image,
+    float* __restrict__ t_ws, float* __restrict__ t_user, uint32_t* __restrict__ ncontrib) {
+  constexpr int PPL = TileGeom<TW, TH>::PPL;
+  constexpr int RSTEP = TileGeom<TW, TH>::RSTEP;
+  constexpr int PER_LANE = BATCH / 64;
+  const int lane = threadIdx.x;
+  const DevView& V = views[view_of_tile(views, n_views, tile)];
   const uint32_t lt = tile - V.tile_base;
   const int ty = int(lt) / V.tiles_x, tx = int(lt) - ty * V.tiles_x;
-  const int px = tx * TW + int(threadIdx.x) % TW, py = ty * TH + int(threadIdx.x) / TW;
-  const bool inside = px < V.W && py < V.H;
-  const float fx = float(px) + 0.5f, fy = float(py) + 0.5f;
+  const int px = tx * TW + lane % TW;
+  const int py0 = ty * TH + lane / TW;
+  const float fx = float(px) + 0.5f;
+  float T[PPL], cr[PPL], cg[PPL], cb[PPL];
+  uint32_t last[PPL];
+  uint32_t done = 0;   // bit k: pixel k has stopped (or lies outside the image)
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    T[k] = 1.0f; cr[k] = cg[k] = cb[k] = 0.0f; last[k] = 0;
+    if (px >= V.W || py0 + k * RSTEP >= V.H) done |= 1u << k;
+  }
+  constexpr uint32_t kAll = (PPL == 32) ? 0xffffffffu : ((1u << PPL) - 1u);
   const uint32_t start = ranges[2 * size_t(tile)], end = ranges[2 * size_t(tile) + 1];
-  float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
-  uint32_t last = 0;
-  bool done = !inside;
-  for (uint32_t b0 = start; b0 < end; b0 += NT) {
-    if (__syncthreads_count(done) == NT) break;
-    const uint32_t idx = b0 + threadIdx.x;
-    if (idx < end) {
-      const Staged st = stage_record(records, values[idx]);
-      s0[threadIdx.x] = st.g0;
-      s1[threadIdx.x] = st.g1;
-      s2[threadIdx.x] = st.g2;
+  for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
+    if (__ballot(done != kAll) == 0ull) break;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < PER_LANE; ++m) {
+      const uint32_t idx = b0 + uint32_t(m * 64 + lane);
+      if (idx < end) {
+        const Staged st = stage_record(records, values[idx]);
+        s0[m * 64 + lane] = st.g0;
+        s1[m * 64 + lane] = st.g1;
+        s2[m * 64 + lane] = st.g2;
+      }
     }
     __syncthreads();
-    if (!done) {
-      const int nb = int(min(uint32_t(NT), end - b0));
-      for (int j = 0; j < nb; ++j) {
-        const float4 g0 = s0[j], g1 = s1[j];
-        const float dx = fx - g0.x, dy = fy - g0.y;
-        const float r = eval_r(g0, g1.x, dx, dy);
+    if (done == kAll) continue;
+    const int nb = int(min(uint32_t(BATCH), end - b0));
+    for (int j = 0; j < nb; ++j) {
+      const float4 g0 = s0[j], g1 = s1[j];
+      const ColTerms ct = col_terms(g0, fx - g0.x);
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        if (done & (1u << k)) continue;
+        const float dy = float(py0 + k * RSTEP) + 0.5f - g0.y;
+        const float r = eval_r(ct, g1.x, dy);
         if (!(r <= g1.y)) continue;
         float l2;
         const float sigma = eval_sigma(r, g1.z, g1.w, &l2);
         const float alpha = fminf(kAlphaMax, sigma);
         if (alpha < kAlphaMin) continue;
-        const float test = T * (1.0f - alpha);
-        if (test < kTStop) { done = true; break; }
+        const float test = T[k] * (1.0f - alpha);
+        if (test < kTStop) { done |= 1u << k; continue; }
         const float4 g2 = s2[j];
-        const float w = alpha * T;
-        cr += g2.x * w;
-        cg += g2.y * w;
-        cb += g2.z * w;
-        T = test;
-        last = b0 - start + uint32_t(j) + 1u;
+        const float w = alpha * T[k];
+        cr[k] += g2.x * w;
+        cg[k] += g2.y * w;
+        cb[k] += g2.z * w;
+        T[k] = test;
+        last[k] = b0 - start + uint32_t(j) + 1u;
       }
+      if (done == kAll) break;
     }
   }
-  if (inside) {
-    const size_t pix = size_t(V.pix_base) + size_t(py) * V.W + px;
-    image[3 * pix] = cr;
-    image[3 * pix + 1] = cg;
-    image[3 * pix + 2] = cb;
-    t_ws[pix] = T;
-    if (t_user) t_user[pix] = T;
-    ncontrib[pix] = last;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int py = py0 + k * RSTEP;
+    if (px < V.W && py < V.H) {
+      const size_t pix = size_t(V.pix_base) + size_t(py) * V.W + px;
+      image[3 * pix] = cr[k];
+      image[3 * pix + 1] = cg[k];
+      image[3 * pix + 2] = cb[k];
+      t_ws[pix] = T[k];
+      if (t_user) t_user[pix] = T[k];
+      ncontrib[pix] = last[k];
+    }
   }
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Next tile for this workgroup: blockIdx.x on the first visit without a work
+// queue, else the next index of the queue counter (lane 0 takes it, the
+// wavefront shares it).
+__device__ __forceinline__ uint32_t next_tile(uint32_t* work, bool first) {
+  if (!work) return first ? blockIdx.x : 0xffffffffu;
+  uint32_t t = 0;
+  if (threadIdx.x == 0) t = atomicAdd(work, 1u);
+  return uint32_t(__shfl(int(t), 0, 64));
 }
 
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH) raster_bwd_kernel(
+template <int TW, int TH, int BATCH>
+__global__ void __launch_bounds__(64) raster_fwd_kernel(
     const float* __restrict__ records, const uint32_t* __restrict__ values,
     const uint32_t* __restrict__ ranges, const DevView* __restrict__ views, int n_views,
-    const float* __restrict__ t_ws, const uint32_t* __restrict__ ncontrib,
-    const float* __restrict__ d_image, const float* __restrict__ d_tfinal,
-    const float* __restrict__ l1_image, const float* __restrict__ l1_target, float l1_scale,
-    float* __restrict__ grad2d) {
-  constexpr int NT = TW * TH;
-  __shared__ float4 s0[NT], s1[NT], s2[NT];
-  __shared__ uint32_t s_max;
-  const uint32_t tile = blockIdx.x;
-  const int vi = view_of_tile(views, n_views, tile);
-  const DevView& V = views[vi];
+    uint32_t n_tiles, uint32_t* __restrict__ work, float* __restrict__ image,
+    float* __restrict__ t_ws, float* __restrict__ t_user, uint32_t* __restrict__ ncontrib) {
+  __shared__ float4 s0[BATCH], s1[BATCH], s2[BATCH];
+  for (uint32_t tile = next_tile(work, true); tile < n_tiles; tile = next_tile(work, false))
+    raster_fwd_tile<TW, TH, BATCH>(tile, s0, s1, s2, records, values, ranges, views, n_views,
+                                   image, t_ws, t_user, ncontrib);
+}
+
+// Inclusive sum over each 16-lane row by a DPP row_shr scan: lane 15 of a row
+// (lanes 15, 31, 47, 63) ends with the row's total.
+template <int CTRL>
+__device__ __forceinline__ float dpp_shr(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float row_scan(float x) {
+  x += dpp_shr<0x111>(x);   // row_shr:1
+  x += dpp_shr<0x112>(x);   // row_shr:2
+  x += dpp_shr<0x114>(x);   // row_shr:4
+  x += dpp_shr<0x118>(x);   // row_shr:8
+  return x;
+}
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = max(x, uint32_t(__shfl_xor(int(x), o, 64)));
+  return x;
+}
+
+template <int TW, int TH, int BATCH>
+__device__ __forceinline__ void raster_bwd_tile(
+    uint32_t tile, float4* s0, float4* s1, float4* s2, float* s_rows,
+    const float* __restrict__ records,
+    const uint32_t* __restrict__ values, const uint32_t* __restrict__ ranges,
+    const DevView* __restrict__ views, int n_views, const float* __restrict__ t_ws,
+    const uint32_t* __restrict__ ncontrib, const float* __restrict__ d_image,
+    const float* __restrict__ d_tfinal, const float* __restrict__ l1_image,
+    const float* __restrict__ l1_target, float l1_scale, float* __restrict__ grad2d) {
+  constexpr int PPL = TileGeom<TW, TH>::PPL;
+  constexpr int RSTEP = TileGeom<TW, TH>::RSTEP;
+  constexpr int PER_LANE = BATCH / 64;
+  const int lane = threadIdx.x;
+  const DevView& V = views[view_of_tile(views, n_views, tile)];
   const uint32_t lt = tile - V.tile_base;
   const int ty = int(lt) / V.tiles_x, tx = int(lt) - ty * V.tiles_x;
-  const int px = tx * TW + int(threadIdx.x) % TW, py = ty * TH + int(threadIdx.x) / TW;
-  const bool inside = px < V.W && py < V.H;
-  const float fx = float(px) + 0.5f, fy = float(py) + 0.5f;
-  const uint32_t start = ranges[2 * size_t(tile)], end = ranges[2 * size_t(tile) + 1];
-  if (threadIdx.x == 0) s_max = 0;
-  float Tf = 1.0f, gR = 0.0f, gG = 0.0f, gB = 0.0f, gT = 0.0f;
-  uint32_t last = 0;
-  if (inside) {
-    const size_t pix = size_t(V.pix_base) + size_t(py) * V.W + px;
-    Tf = t_ws[pix];
-    last = ncontrib[pix];
-    if (d_image) {
-      gR = d_image[3 * pix];
-      gG = d_image[3 * pix + 1];
-      gB = d_image[3 * pix + 2];
-      if (d_tfinal) gT = d_tfinal[pix];
-    } else {
-      const float e0 = l1_image[3 * pix] - l1_target[3 * pix];
-      const float e1 = l1_image[3 * pix + 1] - l1_target[3 * pix + 1];
-      const float e2 = l1_image[3 * pix + 2] - l1_target[3 * pix + 2];
-      gR = e0 > 0.0f ? l1_scale : (e0 < 0.0f ? -l1_scale : 0.0f);
-      gG = e1 > 0.0f ? l1_scale : (e1 < 0.0f ? -l1_scale : 0.0f);
-      gB = e2 > 0.0f ? l1_scale : (e2 < 0.0f ? -l1_scale : 0.0f);
+  const int px = tx * TW + lane % TW;
+  const int py0 = ty * TH + lane / TW;
+  const float fx = float(px) + 0.5f;
+  const uint32_t start = ranges[2 * size_t(tile)];
+  float Tf[PPL], T[PPL], Sr[PPL], Sg[PPL], Sb[PPL], gR[PPL], gG[PPL], gB[PPL], gT[PPL];
+  uint32_t last[PPL];
+  uint32_t lane_max = 0;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int py = py0 + k * RSTEP;
+    Tf[k] = 1.0f; gR[k] = gG[k] = gB[k] = gT[k] = 0.0f; last[k] = 0;
+    if (px < V.W && py < V.H) {
+      const size_t pix = size_t(V.pix_base) + size_t(py) * V.W + px;
+      Tf[k] = t_ws[pix];
+      last[k] = ncontrib[pix];
+      if (d_image) {
+        gR[k] = d_image[3 * pix];
+        gG[k] = d_image[3 * pix + 1];
+        gB[k] = d_image[3 * pix + 2];
+        if (d_tfinal) gT[k] = d_tfinal[pix];
+      } else {
+        const float e0 = l1_image[3 * pix] - l1_target[3 * pix];
+        const float e1 = l1_image[3 * pix + 1] - l1_target[3 * pix + 1];
+        const float e2 = l1_image[3 * pix + 2] - l1_target[3 * pix + 2];
+        gR[k] = e0 > 0.0f ? l1_scale : (e0 < 0.0f ? -l1_scale : 0.0f);
+        gG[k] = e1 > 0.0f ? l1_scale : (e1 < 0.0f ? -l1_scale : 0.0f);
+        gB[k] = e2 > 0.0f ? l1_scale : (e2 < 0.0f ? -l1_scale : 0.0f);
+      }
     }
+    T[k] = Tf[k];
+    Sr[k] = Sg[k] = Sb[k] = 0.0f;
+    lane_max = max(lane_max, last[k]);
   }
-  __syncthreads();
-  if (last > 0) atomicMax(&s_max, last);
-  __syncthreads();
-  const uint32_t span = s_max;
-  float T = Tf;                       // transmittance behind the current record
-  float Sr = 0.0f, Sg = 0.0f, Sb = 0.0f;  // colour accumulated behind it
-  const int lane = threadIdx.x & 63;
+  const uint32_t span = wave_max_u32(lane_max);
   for (uint32_t hi = span; hi > 0;) {
-    const uint32_t lo = hi > uint32_t(NT) ? hi - uint32_t(NT) : 0u;
+    const uint32_t lo = hi > uint32_t(BATCH) ? hi - uint32_t(BATCH) : 0u;
     const uint32_t cnt = hi - lo;
     __syncthreads();
-    if (threadIdx.x < cnt) {
-      const Staged st = stage_record(records, values[start + lo + threadIdx.x]);
-      s0[threadIdx.x] = st.g0;
-      s1[threadIdx.x] = st.g1;
-      s2[threadIdx.x] = st.g2;
+#pragma unroll
+    for (int m = 0; m < PER_LANE; ++m) {
+      const uint32_t q = uint32_t(m * 64 + lane);
+      if (q < cnt) {
+        const Staged st = stage_record(records, values[start + lo + q]);
+        s0[q] = st.g0;
+        s1[q] = st.g1;
+        s2[q] = st.g2;
+      }
     }
     __syncthreads();
     for (int j = int(cnt) - 1; j >= 0; --j) {
       const uint32_t pos = lo + uint32_t(j);
+      const float4 g0 = s0[j], g1 = s1[j], g2 = s2[j];
+      const float dx = fx - g0.x;
+      const ColTerms ct = col_terms(g0, dx);
+      const float inv_o = hw_exp2(-g1.z);   // 1 / o: d sigma / d o = sigma / o
+      // per-lane sums over the lane's pixels
+      float a_r = 0.f, a_g = 0.f, a_b = 0.f, a_o = 0.f, a_be = 0.f;
+      float a_dr = 0.f, a_dry = 0.f, a_dryy = 0.f;
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        if (pos >= last[k]) continue;
+        const float dy = float(py0 + k * RSTEP) + 0.5f - g0.y;
+        const float r = eval_r(ct, g1.x, dy);
+        if (!(r <= g1.y)) continue;
+        float l2;
+        const float sigma = eval_sigma(r, g1.z, g1.w, &l2);
+        const float alpha = fminf(kAlphaMax, sigma);
+        if (alpha < kAlphaMin) continue;
+        any = true;
+        const float oma = 1.0f - alpha;
+        const float ioma = fast_rcp(oma);
+        const float Ti = T[k] * ioma;
+        const float w = alpha * Ti;
+        a_r += gR[k] * w;
+        a_g += gG[k] * w;
+        a_b += gB[k] * w;
+        const float dalpha = Ti * (gR[k] * (g2.x - Sr[k]) + gG[k] * (g2.y - Sg[k]) +
+                                   gB[k] * (g2.z - Sb[k])) - gT[k] * Tf[k] * ioma;
+        Sr[k] = alpha * g2.x + oma * Sr[k];
+        Sg[k] = alpha * g2.y + oma * Sg[k];
+        Sb[k] = alpha * g2.z + oma * Sb[k];
+        T[k] = Ti;
+        if (sigma < kAlphaMax) {
+          a_o += dalpha * sigma;                            // times 1/o after the sums
+          a_be += dalpha * sigma * l2 * 0.69314718f;        // d sigma / d beta
+          const float dr = -dalpha * g1.w * sigma * fast_rcp(1.0f - r);  // d sigma / d r
+          a_dr += dr;
+          a_dry += dr * dy;
+          a_dryy += dr * dy * dy;
+        }
+      }
+      if (__ballot(any) == 0ull) continue;
+      // record-field gradients of this lane: r = a dx^2 + 2 b dx dy + c dy^2
+      const float b = 0.5f * g0.w;
       float gv[kGradFloats];
+      gv[0] = -2.0f * (g0.z * dx * a_dr + b * a_dry);
+      gv[1] = -2.0f * (b * dx * a_dr + g1.x * a_dry);
+      gv[2] = dx * dx * a_dr;
+      gv[3] = 2.0f * dx * a_dry;
+      gv[4] = a_dryy;
+      gv[6] = a_be;
+      gv[7] = a_r;
+      gv[8] = a_g;
+      gv[9] = a_b;
+      gv[5] = a_o * inv_o;
+      // sums over the wavefront: row scans, the four row totals through LDS,
+      // lane q < 10 adds the four totals of field q and issues its atomic
 #pragma unroll
-      for (int k = 0; k < kGradFloats; ++k) gv[k] = 0.0f;
-      bool contrib = false;
-      if (pos < last) {
-        const float4 g0 = s0[j], g1 = s1[j];
-        const float dx = fx - g0.x, dy = fy - g0.y;
-        const float r = eval_r(g0, g1.x, dx, dy);
-        if (r <= g1.y) {
-          float l2;
-          const float sigma = eval_sigma(r, g1.z, g1.w, &l2);
-          const float alpha = fminf(kAlphaMax, sigma);
-          if (alpha >= kAlphaMin) {
-            contrib = true;
-            const float4 g2 = s2[j];
-            const float oma = 1.0f - alpha;
-            const float Ti = T / oma;
-            const float w = alpha * Ti;
-            gv[7] = gR * w;
-            gv[8] = gG * w;
-            gv[9] = gB * w;
-            const float dalpha = Ti * (gR * (g2.x - Sr) + gG * (g2.y - Sg) + gB * (g2.z - Sb)) -
-                                 gT * Tf / oma;
-            Sr = alpha * g2.x + oma * Sr;
-            Sg = alpha * g2.y + oma * Sg;
-            Sb = alpha * g2.z + oma * Sb;
-            T = Ti;
-            if (sigma < kAlphaMax) {
-              const float base = 1.0f - r;
-              gv[5] = dalpha * hw_exp2(g1.w * l2);                  // d sigma / d o = (1-r)^beta
-              gv[6] = dalpha * sigma * l2 * 0.69314718f;            // d sigma / d beta
-              const float dr = -dalpha * g1.w * sigma / base;       // d sigma / d r
-              const float b = 0.5f * g0.w;
-              gv[0] = -2.0f * dr * (g0.z * dx + b * dy);
-              gv[1] = -2.0f * dr * (b * dx + g1.x * dy);
-              gv[2] = dr * dx * dx;
-              gv[3] = 2.0f * dr * dx * dy;
-              gv[4] = dr * dy * dy;
-            }
-          }
+      for (int q = 0; q < kGradFloats; ++q) {
+        const float rs = row_scan(gv[q]);
+        if ((lane & 15) == 15) s_rows[(lane >> 4) * kGradFloats + q] = rs;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      if (lane < kGradFloats) {
+        const float tot = (s_rows[lane] + s_rows[kGradFloats + lane]) +
+                          (s_rows[2 * kGradFloats + lane] + s_rows[3 * kGradFloats + lane]);
+        if (tot != 0.0f) {
+          const uint32_t rec = __float_as_uint(g2.w);
+          atomicAdd(grad2d + size_t(rec) * kGradFloats + lane, tot);
         }
       }
-      if (__ballot(contrib) != 0ull) {
-        const uint32_t rec = __float_as_uint(s2[j].w);
-        float* gp = grad2d + size_t(rec) * kGradFloats;
-#pragma unroll
-        for (int k = 0; k < kGradFloats; ++k) {
-          const float s = wave_sum(gv[k]);
-          if (lane == 0 && s != 0.0f) atomicAdd(gp + k, s);
-        }
-      }
+      __builtin_amdgcn_s_barrier();
     }
     hi = lo;
   }
 }
 
-template <int TW, int TH>
-static hipError_t raster_fwd_t(const float* records, const uint32_t* values, const uint32_t* ranges,
-                               const DevView* views, int n_views, uint32_t n_tiles, float* image,
-                               float* t_ws, float* t_user, uint32_t* ncontrib, hipStream_t st) {
-  hipLaunchKernelGGL((raster_fwd_kernel<TW, TH>), dim3(n_tiles), dim3(TW * TH), 0, st, records,
-                     values, ranges, views, n_views, image, t_ws, t_user, ncontrib);
+template <int TW, int TH, int BATCH>
+__global__ void __launch_bounds__(64) raster_bwd_kernel(
+    const float* __restrict__ records, const uint32_t* __restrict__ values,
+    const uint32_t* __restrict__ ranges, const DevView* __restrict__ views, int n_views,
+    uint32_t n_tiles, uint32_t* __restrict__ work, const float* __restrict__ t_ws,
+    const uint32_t* __restrict__ ncontrib, const float* __restrict__ d_image,
+    const float* __restrict__ d_tfinal, const float* __restrict__ l1_image,
+    const float* __restrict__ l1_target, float l1_scale, float* __restrict__ grad2d) {
+  __shared__ float4 s0[BATCH], s1[BATCH], s2[BATCH];
+  __shared__ float s_rows[4 * kGradFloats];
+  for (uint32_t tile = next_tile(work, true); tile < n_tiles; tile = next_tile(work, false))
+    raster_bwd_tile<TW, TH, BATCH>(tile, s0, s1, s2, s_rows, records, values, ranges, views, n_views, t_ws,
+                                   ncontrib, d_image, d_tfinal, l1_image, l1_target, l1_scale,
+                                   grad2d);
+}
+
+__global__ void reset_counter_kernel(uint32_t* __restrict__ c) {
+  if (threadIdx.x == 0) *c = 0u;
+}
+
+// Launch geometry: one wavefront per tile (grid = tiles), or a persistent
+// grid of `persistent_blocks` wavefronts taking tiles from a queue.
+struct RasterLaunch {
+  uint32_t n_tiles;
+  uint32_t* work;            // queue counter, or nullptr
+  uint32_t grid;
+};
+
+static RasterLaunch raster_geometry(uint32_t n_tiles, uint32_t* work, uint32_t persistent_blocks,
+                                    hipStream_t st) {
+  RasterLaunch g{n_tiles, nullptr, n_tiles};
+  if (work && persistent_blocks > 0 && persistent_blocks < n_tiles) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, work);
+    g.work = work;
+    g.grid = persistent_blocks;
+  }
+  return g;
+}
+
+template <int TW, int TH, int BATCH>
+static hipError_t raster_fwd_t(const RasterLaunch& g, const float* records, const uint32_t* values,
+                               const uint32_t* ranges, const DevView* views, int n_views,
+                               float* image, float* t_ws, float* t_user, uint32_t* ncontrib,
+                               hipStream_t st) {
+  hipLaunchKernelGGL((raster_fwd_kernel<TW, TH, BATCH>), dim3(g.grid), dim3(64), 0, st, records,
+                     values, ranges, views, n_views, g.n_tiles, g.work, image, t_ws, t_user,
+                     ncontrib);
   return hipGetLastError();
 }
 
-template <int TW, int TH>
-static hipError_t raster_bwd_t(const float* records, const uint32_t* values, const uint32_t* ranges,
-                               const DevView* views, int n_views, uint32_t n_tiles,
+template <int TW, int TH, int BATCH>
+static hipError_t raster_bwd_t(const RasterLaunch& g, const float* records, const uint32_t* values,
+                               const uint32_t* ranges, const DevView* views, int n_views,
                                const float* t_ws, const uint32_t* ncontrib, const float* d_image,
                                const float* d_tfinal, const float* l1_image,
                                const float* l1_target, float l1_scale, float* grad2d,
                                hipStream_t st) {
-  hipLaunchKernelGGL((raster_bwd_kernel<TW, TH>), dim3(n_tiles), dim3(TW * TH), 0, st, records,
-                     values, ranges, views, n_views, t_ws, ncontrib, d_image, d_tfinal, l1_image,
-                     l1_target, l1_scale, grad2d);
+  hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, BATCH>), dim3(g.grid), dim3(64), 0, st, records,
+                     values, ranges, views, n_views, g.n_tiles, g.work, t_ws, ncontrib, d_image,
+                     d_tfinal, l1_image, l1_target, l1_scale, grad2d);
   return hipGetLastError();
 }
 
-hipError_t launch_raster_fwd(int tw, int th, const float* records, const uint32_t* values,
+#define UBS_TILE_DISPATCH(FN, ...)                                                     \
+  do {                                                                                 \
+    const int bd = batch <= 64 ? 64 : (batch <= 128 ? 128 : 256);                      \
+    if (tw == 16 && th == 16) {                                                        \
+      if (bd == 64) return FN<16, 16, 64>(__VA_ARGS__);                                \
+      if (bd == 128) return FN<16, 16, 128>(__VA_ARGS__);                              \
+      return FN<16, 16, 256>(__VA_ARGS__);                                             \
+    }                                                                                  \
+    if (tw == 16 && th == 8) {                                                         \
+      if (bd == 64) return FN<16, 8, 64>(__VA_ARGS__);                                 \
+      if (bd == 128) return FN<16, 8, 128>(__VA_ARGS__);                               \
+      return FN<16, 8, 256>(__VA_ARGS__);                                              \
+    }                                                                                  \
+    if (tw == 8 && th == 8) {                                                          \
+      if (bd == 64) return FN<8, 8, 64>(__VA_ARGS__);                                  \
+      if (bd == 128) return FN<8, 8, 128>(__VA_ARGS__);                                \
+      return FN<8, 8, 256>(__VA_ARGS__);                                               \
+    }                                                                                  \
+    if (tw == 32 && th == 16) {                                                        \
+      if (bd == 64) return FN<32, 16, 64>(__VA_ARGS__);                                \
+      if (bd == 128) return FN<32, 16, 128>(__VA_ARGS__);                              \
+      return FN<32, 16, 256>(__VA_ARGS__);                                             \
+    }                                                                                  \
+    return hipErrorInvalidValue;                                                       \
+  } while (0)
+
+hipError_t launch_raster_fwd(int tw, int th, int batch, uint32_t persistent_blocks,
+                             uint32_t* work, const float* records, const uint32_t* values,
                              const uint32_t* ranges, const DevView* views, int n_views,
                              uint32_t n_tiles, float* image, float* t_ws, float* t_user,
                              uint32_t* ncontrib, hipStream_t st) {
   if (n_tiles == 0) return hipSuccess;
-  if (tw == 16 && th == 16)
-    return raster_fwd_t<16, 16>(records, values, ranges, views, n_views, n_tiles, image, t_ws, t_user, ncontrib, st);
-  if (tw == 16 && th == 8)
-    return raster_fwd_t<16, 8>(records, values, ranges, views, n_views, n_tiles, image, t_ws, t_user, ncontrib, st);
-  if (tw == 8 && th == 8)
-    return raster_fwd_t<8, 8>(records, values, ranges, views, n_views, n_tiles, image, t_ws, t_user, ncontrib, st);
-  if (tw == 32 && th == 16)
-    return raster_fwd_t<32, 16>(records, values, ranges, views, n_views, n_tiles, image, t_ws, t_user, ncontrib, st);
-  return hipErrorInvalidValue;
+  const RasterLaunch g = raster_geometry(n_tiles, work, persistent_blocks, st);
+  UBS_TILE_DISPATCH(raster_fwd_t, g, records, values, ranges, views, n_views, image, t_ws, t_user,
+                    ncontrib, st);
 }
 
-hipError_t launch_raster_bwd(int tw, int th, const float* records, const uint32_t* values,
+hipError_t launch_raster_bwd(int tw, int th, int batch, uint32_t persistent_blocks,
+                             uint32_t* work, const float* records, const uint32_t* values,
                              const uint32_t* ranges, const DevView* views, int n_views,
                              uint32_t n_tiles, const float* t_ws, const uint32_t* ncontrib,
                              const float* d_image, const float* d_tfinal, const float* l1_image,
                              const float* l1_target, float l1_scale, float* grad2d,
                              hipStream_t st) {
   if (n_tiles == 0) return hipSuccess;
-  if (tw == 16 && th == 16)
-    return raster_bwd_t<16, 16>(records, values, ranges, views, n_views, n_tiles, t_ws, ncontrib, d_image, d_tfinal, l1_image, l1_target, l1_scale, grad2d, st);
-  if (tw == 16 && th == 8)
-    return raster_bwd_t<16, 8>(records, values, ranges, views, n_views, n_tiles, t_ws, ncontrib, d_image, d_tfinal, l1_image, l1_target, l1_scale, grad2d, st);
-  if (tw == 8 && th == 8)
-    return raster_bwd_t<8, 8>(records, values, ranges, views, n_views, n_tiles, t_ws, ncontrib, d_image, d_tfinal, l1_image, l1_target, l1_scale, grad2d, st);
-  if (tw == 32 && th == 16)
-    return raster_bwd_t<32, 16>(records, values, ranges, views, n_views, n_tiles, t_ws, ncontrib, d_image, d_tfinal, l1_image, l1_target, l1_scale, grad2d, st);
-  return hipErrorInvalidValue;
+  const RasterLaunch g = raster_geometry(n_tiles, work, persistent_blocks, st);
+  UBS_TILE_DISPATCH(raster_bwd_t, g, records, values, ranges, views, n_views, t_ws, ncontrib,
+                    d_image, d_tfinal, l1_image, l1_target, l1_scale, grad2d, st);
 }
 
 }  // namespace ubs

@@ -23,7 +23,7 @@ REC_FIELDS = ("mx", "my", "a", "b", "c", "rho", "o", "beta", "r", "g", "bl", "de
 class Tuning:
     tile_w: int = 16
     tile_h: int = 16
-    batch_depth: int = 256
+    batch_depth: int = 64
     digit_bits: int = 8
     pair_capacity: int = 0          # 0: sized from the frame
     flags: int = 0
@@ -155,7 +155,8 @@ class Renderer:
         raw = self.ws[off:off + 64].cpu().numpy().tobytes()
         st = _lib.UbsStatusBlock.from_buffer_copy(raw)
         return {"pairs_needed": int(st.pairs_needed), "overflow": int(st.overflow),
-                "n_nonfinite": int(st.n_nonfinite), "n_visible": int(st.n_visible)}
+                "n_nonfinite": int(st.n_nonfinite), "n_visible": int(st.n_visible),
+                "sort_stalled": int(st.sort_stalled)}
 
     def region(self, off: int, count: int, dtype: torch.dtype) -> torch.Tensor:
         esz = torch.tensor([], dtype=dtype).element_size()
@@ -253,3 +254,76 @@ def render(renderer: Renderer, params: Sequence[torch.Tensor], dims: Sequence[in
            rots: Sequence[int], views: Sequence):
     """Differentiable render of every view; returns (image, t_final) flat over views."""
     return UBSRenderFunction.apply(renderer, tuple(dims), tuple(rots), tuple(views), *params)
+
+
+class GraphFrame:
+    """One forward+backward frame captured in a HIP graph and replayed.
+
+    The frame is first run eagerly (sizing the workspace and the pair
+    capacity), then the four calls are captured with ``torch.cuda.graph``.
+    Every replay re-renders from the current contents of the parameter
+    tensors and writes ``image``, ``t_final`` and the ``dparams`` tensors.
+    The pair capacity is fixed at capture: after a replay, ``status()``
+    reports ``overflow`` if a frame needed more (re-create the GraphFrame).
+    Loss: ``l1_target`` (fused L1 gradient) or ``d_image`` (a tensor whose
+    contents are read at each replay).
+    """
+
+    def __init__(self, renderer: Renderer, scenes: Sequence[SceneRef], views: Sequence, *,
+                 l1_target: Optional[torch.Tensor] = None, d_image: Optional[torch.Tensor] = None,
+                 backward: bool = True, headroom: float = 1.25, stage_events=None):
+        if backward and (l1_target is None) == (d_image is None):
+            raise ValueError("give exactly one of l1_target or d_image")
+        self.r = renderer
+        self.views = list(views)
+        self.l1_target, self.d_image = l1_target, d_image
+        self.image, self.t_final = renderer.forward(scenes, self.views)   # sizes the capacity
+        st = renderer.status()
+        cap = max(renderer.capacity, int(st["pairs_needed"] * headroom) + 1024)
+        if cap != renderer.capacity:
+            renderer.capacity = cap
+            self.image, self.t_final = renderer.forward(scenes, self.views)
+        self.frame = renderer.frame
+        self.dparams = []
+        for k, s in enumerate(self.frame.scenes):
+            g = torch.empty_like(s.params)
+            self.frame.set_dparams(k, g)
+            self.dparams.append(g)
+        self.backward = backward
+        self._step()                       # eager warm-up of the exact sequence
+        torch.cuda.synchronize()
+        self.graph = self.capture(stage_events)
+
+    def capture(self, stage_events=None) -> "torch.cuda.CUDAGraph":
+        """Captures the frame once more into a new graph; with ``stage_events``
+        (a ``StageTimer`` slot) the graph also records the per-stage events."""
+        g = torch.cuda.CUDAGraph()
+        self.frame.c.stage_events = stage_events
+        try:
+            with torch.cuda.graph(g):
+                self._step()
+        finally:
+            self.frame.c.stage_events = None
+        torch.cuda.synchronize()
+        return g
+
+    def step(self) -> None:
+        """Runs the frame eagerly (the sequence the graphs replay)."""
+        self._step()
+
+    def _step(self) -> None:
+        r, f = self.r, self.frame
+        r.preprocess(f)
+        r.bin_sort(f)
+        r.render_fwd(f, self.image, self.t_final)
+        if self.backward:
+            if self.l1_target is not None:
+                r.render_bwd(f, l1_image=self.image, l1_target=self.l1_target)
+            else:
+                r.render_bwd(f, self.d_image)
+
+    def replay(self) -> None:
+        self.graph.replay()
+
+    def status(self) -> dict:
+        return self.r.status()

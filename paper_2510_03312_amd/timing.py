@@ -49,8 +49,12 @@ class StageTimer:
             self.arrays.append(arr)
         self.used = [set() for _ in range(slots)]
 
+    def slot(self, slot: int):
+        """The ``ubs_frame.stage_events`` pointer of one slot."""
+        return ctypes.cast(self.arrays[slot], ctypes.POINTER(ctypes.c_void_p))
+
     def attach(self, frame_c, slot: int) -> None:
-        frame_c.stage_events = ctypes.cast(self.arrays[slot], ctypes.POINTER(ctypes.c_void_p))
+        frame_c.stage_events = self.slot(slot)
 
     @staticmethod
     def detach(frame_c) -> None:

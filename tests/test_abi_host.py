@@ -56,7 +56,7 @@ def test_ctypes_structs_match_the_header(tmp_path):
         "ubs_layout": ["bytes", "n_records", "n_tiles", "n_pixels", "pair_capacity", "key_bits",
                        "n_views", "off_status", "off_records", "off_keys", "off_values",
                        "off_ranges", "off_ncontrib", "off_grad2d"],
-        "ubs_status_block": ["pairs_needed", "overflow", "n_nonfinite", "n_visible"],
+        "ubs_status_block": ["pairs_needed", "overflow", "n_nonfinite", "n_visible", "sort_stalled"],
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void){"]
     for s, fs in fields.items():
@@ -125,6 +125,7 @@ def test_size_query_without_gpu():
 @pytest.mark.parametrize("mutate,code", [
     (lambda f: setattr(f.c.tuning, "tile_w", 12), _lib.UBS_ERR_UNSUPPORTED),
     (lambda f: setattr(f.c.tuning, "digit_bits", 12), _lib.UBS_ERR_UNSUPPORTED),
+    (lambda f: setattr(f.c.tuning, "batch_depth", 96), _lib.UBS_ERR_UNSUPPORTED),
     (lambda f: setattr(f.c.tuning, "pair_capacity", -1), _lib.UBS_ERR_ARG),
     (lambda f: setattr(f._sc[0], "dim", 5), _lib.UBS_ERR_UNSUPPORTED),
     (lambda f: setattr(f._sc[0], "dim", 9), _lib.UBS_ERR_ARG),
