@@ -38,10 +38,11 @@ def ambiguous_records(out: dict) -> np.ndarray:
     return amb
 
 
-def _amb_records(out: dict, amb: np.ndarray) -> np.ndarray:
-    """Records with the would-be splat of each ambiguous-but-culled primitive
-    (rho = 0: never contributes, only flags the pixels it could touch)."""
-    rec = out["rec"].detach().numpy().copy()
+def _amb_records(out: dict, amb: np.ndarray, rec: np.ndarray) -> np.ndarray:
+    """A copy of the records ``rec`` with the would-be splat of each
+    ambiguous-but-culled primitive (rho = 0: never contributes, only flags
+    the pixels it could touch)."""
+    rec = rec.copy()
     idx = np.flatnonzero(amb & ~out["valid"].numpy())
     if idx.size:
         Sp = out["Sp"].detach().numpy()[idx]
@@ -81,7 +82,7 @@ def render(params: np.ndarray, dim: int, rot: int, view, *, d_image: Optional[np
     if record_f32:
         rec = rec.astype(np.float32).astype(np.float64)
     amb = ambiguous_records(out)
-    rec_f = _amb_records(out, amb) if amb.any() else rec
+    rec_f = _amb_records(out, amb, rec) if amb.any() else rec
     W, H = view.width, view.height
     img, tf, nc, fl = raster.render_fwd(rec_f, W, H, amb=amb if amb.any() else None,
                                         rows=rows, bands=bands)
