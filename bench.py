@@ -31,6 +31,27 @@ if ROOT not in sys.path:
 
 METRIC = "fwd+bwd frames/s at 1M 7-D Beta prims, 1080p, 1 MI355X; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
+# Vector ALU peak in lane-operations: 256 CUs x 64 lanes per clock x 2.4 GHz
+# (non-packed fp32; the kernels are built without packed fp32 instructions).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+# Algorithmic VALU lane-operations of the backward raster per unit of work,
+# counted from the arithmetic itself (an FMA, add, mul, min or compare = 1;
+# exp2, log2 and reciprocal = 4, they issue at quarter rate).  Only work the
+# adjoint needs is counted: the cross-lane sums, the LDS staging and the
+# lanes idle under divergence are overheads of the implementation.
+#   eval     (pixel, record) visited before the pixel's last contributor:
+#            dy, r = A + dy (B + c dy), support test                      4
+#   support  r <= rho: 1 - r, log2, fma with beta and log2 o, exp2,
+#            min 0.99, alpha test                                         12
+#   contrib  alpha >= 1/255: 1 - alpha, rcp, T/(1-alpha), weight, three
+#            colour-gradient sums, d alpha (11), running colour (6)       27
+#   grad     sigma < 0.99 as well: opacity and beta terms, d sigma / d r
+#            (rcp of 1 - r) and the three moment sums                     15
+#   pair     per (tile, record): dx and the column terms of the tile's 16
+#            pixel columns (4 each), 1/o, the ten sums turned into the
+#            record-field gradients (14)                                  64 + 4 + 14
+BWD_OPS = {"eval": 4, "support": 12, "contrib": 27, "grad": 15, "pair": 82}
 
 WORKLOADS = {
     "headline": ("headline", "1,000,000 7-D Beta primitives (quaternion rotation), one "
@@ -95,6 +116,51 @@ def stage_bytes(stage: str, c: dict) -> float:
         # written, liveness flags and the live records' gradients read
         "pre_bwd": 4.0 * F * Pv + 4.0 * F * P + 8.0 * R + 40.0 * Pv,
     }[stage]
+
+
+def raster_bwd_work(r, view, n_pairs: int, tile: int = 16, chunk: int = 8192) -> dict:
+    """Counts the backward raster's units of work on the frame left in the
+    workspace (one view, 16x16 tiles), with the same per-pixel decisions in
+    float32 torch ops on the device, outside the timed region."""
+    import torch
+    rec = r.records()
+    rng = r.ranges().long()
+    vals = r.sorted_pairs(n_pairs)[1].long()
+    last = r.ncontrib().long()
+    W, H = view.width, view.height
+    tiles_x = (W + tile - 1) // tile
+    counts = rng[:, 1] - rng[:, 0]
+    tile_of = torch.repeat_interleave(torch.arange(rng.shape[0], device=rec.device), counts)
+    pos_all = torch.arange(n_pairs, device=rec.device) - rng[tile_of, 0]
+    lane = torch.arange(tile * tile, device=rec.device)
+    lx, ly = lane % tile, lane // tile
+    tot = {k: 0 for k in ("eval", "support", "contrib", "grad", "pair", "pairs_active")}
+    tot["pair"] = n_pairs
+    for c0 in range(0, n_pairs, chunk):
+        t = tile_of[c0:c0 + chunk]
+        pos = pos_all[c0:c0 + chunk, None]
+        g = rec[vals[c0:c0 + chunk]]
+        px = (t % tiles_x)[:, None] * tile + lx[None]
+        py = (t // tiles_x)[:, None] * tile + ly[None]
+        inside = (px < W) & (py < H)
+        pix = (py.clamp(max=H - 1) * W + px.clamp(max=W - 1))
+        ev = inside & (pos < last[pix])
+        dx = px.float() + 0.5 - g[:, 0:1]
+        dy = py.float() + 0.5 - g[:, 1:2]
+        rr = g[:, 2:3] * dx * dx + 2.0 * g[:, 3:4] * dx * dy + g[:, 4:5] * dy * dy
+        sup = ev & (rr <= g[:, 5:6])
+        sigma = g[:, 6:7] * torch.clamp(1.0 - rr, min=0.0) ** g[:, 7:8]
+        con = sup & (torch.clamp(sigma, max=0.99) >= 1.0 / 255.0)
+        tot["eval"] += int(ev.sum())
+        tot["support"] += int(sup.sum())
+        tot["contrib"] += int(con.sum())
+        tot["grad"] += int((con & (sigma < 0.99)).sum())
+        tot["pairs_active"] += int(con.any(dim=1).sum())
+    tot["lane_ops"] = sum(BWD_OPS[k] * tot[k] for k in BWD_OPS)
+    # every visit is of a record before its pixel's last contributor: the
+    # visits must add up to the sum of the per-pixel contributor counts
+    tot["sum_ncontrib"] = int(last[:W * H].sum())
+    return tot
 
 
 def cpu_baseline(cfg, rows: int = 24, sub: int = 100_000) -> dict:
@@ -210,6 +276,18 @@ def run_single(args, name, desc):
     dom = max(stages_ms, key=stages_ms.get)
     ach = stage_bytes(dom, c) / (stages_ms[dom] * 1e-3) / 1e9
     frame_bytes = sum(stage_bytes(s, c) for s in stages_ms)
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
+            "traffic": recorded_traffic(name, dom)}
+    if dom == "raster_bwd" and view.width * view.height > 0:
+        # the backward raster is bound by vector ALU work, not by bytes
+        work = raster_bwd_work(r, view, c["K"])
+        tops = work["lane_ops"] / (stages_ms[dom] * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(tops, 3), "peak": VALU_PEAK_TOPS,
+                "unit": "T lane-ops/s", "frac": round(tops / VALU_PEAK_TOPS, 4),
+                "traffic": recorded_traffic(name, dom), "work": work,
+                "hbm": {"achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(ach / HBM_PEAK_GBS, 5)}}
     res = {
         "metric": METRIC if name == "headline" else f"{'fwd+bwd' if backward else 'fwd'} frames/s ({name})",
         "value": round(1000.0 / ms, 3), "unit": "frames/s", "n_gpus": 1,
@@ -219,9 +297,7 @@ def run_single(args, name, desc):
         "config": {"workload": desc, "primitives": sc.n, "dim": sc.dim, "params_per_prim": c["F"],
                    "width": view.width, "height": view.height, "views": 1, "pairs": c["K"],
                    "visible": c["Pv"], "launch": "eager" if args.eager else "hip-graph"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
-                     "traffic": recorded_traffic(name, dom)},
+        "roofline": roof,
         "kernel_sources": kernel_sources_digest(),
         "frame_hbm_frac": round(frame_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
         "stages_ms": {k: round(v, 4) for k, v in stages_ms.items()},

@@ -185,18 +185,22 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(
                                    image, t_ws, t_user, ncontrib);
 }
 
-// Inclusive sum over each 16-lane row by a DPP row_shr scan: lane 15 of a row
-// (lanes 15, 31, 47, 63) ends with the row's total.
+// Inclusive sums over each 16-lane row by DPP row_shr scans, of N values at
+// once: lane 15 of a row (lanes 15, 31, 47, 63) ends with the row's totals.
 template <int CTRL>
 __device__ __forceinline__ float dpp_shr(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
-__device__ __forceinline__ float row_scan(float x) {
-  x += dpp_shr<0x111>(x);   // row_shr:1
-  x += dpp_shr<0x112>(x);   // row_shr:2
-  x += dpp_shr<0x114>(x);   // row_shr:4
-  x += dpp_shr<0x118>(x);   // row_shr:8
-  return x;
+template <int N>
+__device__ __forceinline__ void row_scan_all(float* v) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_shr<0x111>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_shr<0x112>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_shr<0x114>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_shr<0x118>(v[q]);
 }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -330,10 +334,12 @@ __device__ __forceinline__ void raster_bwd_tile(
       gv[5] = a_o * inv_o;
       // sums over the wavefront: row scans, the four row totals through LDS,
       // lane q < 10 adds the four totals of field q and issues its atomic
+      // (the ten scans are independent: one DPP step of every field before
+      // the next step, so no step waits on the previous one's result)
+      row_scan_all<kGradFloats>(gv);
+      if ((lane & 15) == 15) {
 #pragma unroll
-      for (int q = 0; q < kGradFloats; ++q) {
-        const float rs = row_scan(gv[q]);
-        if ((lane & 15) == 15) s_rows[(lane >> 4) * kGradFloats + q] = rs;
+        for (int q = 0; q < kGradFloats; ++q) s_rows[(lane >> 4) * kGradFloats + q] = gv[q];
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __builtin_amdgcn_s_barrier();
