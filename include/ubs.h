@@ -120,7 +120,7 @@ typedef struct {
 /*
  * Tuning.  tile_w x tile_h in {8x8, 16x8, 16x16, 32x16} (one wavefront of 64
  * lanes per tile); batch_depth in {64, 128, 256} (records staged in LDS per
- * round); digit_bits in [4, 8] (radix-sort digit width).
+ * round); digit_bits in [4, 8] (digit width of the radix sort of long tile segments).
  * pair_capacity: number of (tile, primitive) pairs the workspace holds; if a
  * frame needs more, ubs_bin_sort sets the status overflow flag, emits no
  * pairs and the render calls draw nothing (rerun with a larger capacity,
@@ -150,9 +150,9 @@ enum {
   UBS_STAGE_PREPROCESS = 0,   /* ubs_preprocess: per-primitive kernel        */
   UBS_STAGE_BIN_COUNT = 1,    /* ubs_bin_sort: tile counts                    */
   UBS_STAGE_SCAN = 2,         /* ubs_bin_sort: exclusive scan of the counts   */
-  UBS_STAGE_BIN_EMIT = 3,     /* ubs_bin_sort: key/value emission             */
-  UBS_STAGE_SORT = 4,         /* ubs_bin_sort: all radix passes               */
-  UBS_STAGE_RANGES = 5,       /* ubs_bin_sort: per-tile ranges                */
+  UBS_STAGE_BIN_EMIT = 3,     /* ubs_bin_sort: pairs into tile segments       */
+  UBS_STAGE_SORT = 4,         /* ubs_bin_sort: per-tile depth sort + ranges   */
+  UBS_STAGE_RANGES = 5,       /* reserved (ranges come with the sort)         */
   UBS_STAGE_RASTER_FWD = 6,   /* ubs_render_fwd                               */
   UBS_STAGE_GRAD_CLEAR = 7,   /* ubs_render_bwd: clear the record gradients   */
   UBS_STAGE_RASTER_BWD = 8,   /* ubs_render_bwd: compositing adjoint          */
@@ -216,8 +216,7 @@ typedef struct {
   uint32_t overflow;         /* 1 if pairs_needed > pair_capacity */
   uint32_t n_nonfinite;      /* primitives with non-finite parameters (culled) */
   uint32_t n_visible;        /* records that survived culling */
-  uint32_t sort_stalled;     /* 1 if a radix-sort look-back wait hit its bound
-                                (the sorted output is then invalid) */
+  uint32_t sort_stalled;     /* reserved, always 0 */
   uint32_t _pad[10];
 } ubs_status_block;
 
@@ -239,13 +238,17 @@ ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
                           ubs_layout* layout, void* stream);
 
 /*
- * ubs_bin_sort -- tile binning and (tile, depth) radix sort.
+ * ubs_bin_sort -- tile binning and (tile, depth) sort.
  * Reads the records in ws (written by ubs_preprocess, or by the caller in
  * the documented record format after a ubs_preprocess call on the same
  * frame).  A record overlaps a tile iff the minimum of r over the rectangle
  * spanned by the tile's pixel centres (clipped to the image) is at most
  * rho (1 + 2^-10), evaluated in float64 without contraction.  Keys are
- * sorted ascending; equal keys keep record-index order.
+ * sorted ascending; equal keys keep record-index order (the result is that
+ * of a stable sort of the keys emitted record by record).  The pairs are
+ * counted per tile, placed in per-tile segments and each segment sorted by
+ * (depth, record); tuning.digit_bits sets the digit width of the radix sort
+ * used for segments longer than 4096 pairs.
  */
 ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, void* stream);
 

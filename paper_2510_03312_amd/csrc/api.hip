@@ -19,20 +19,18 @@ hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const 
 hipError_t launch_compact(const uint32_t* flags, const uint32_t* offsets, uint32_t n,
                           uint32_t* list, hipStream_t st);
 hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
-                            uint32_t n_records, uint32_t* counts, hipStream_t st);
+                            uint32_t n_records, uint32_t* tile_counts, hipStream_t st);
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
                        DevStatus* status, unsigned long long capacity, hipStream_t st,
                        unsigned long long* total_out);
 hipError_t launch_bin_emit(const float* records, const DevView* views, int n_views,
-                           uint32_t n_records, const uint32_t* offsets, const DevStatus* status,
-                           unsigned long long* keys, uint32_t* values, hipStream_t st);
+                           uint32_t n_records, uint32_t* tile_cursor, const DevStatus* status,
+                           unsigned long long* comp, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
-hipError_t launch_ranges(const unsigned long long* keys, const DevStatus* status, uint32_t* ranges,
-                         size_t n_tiles, unsigned long long capacity, hipStream_t st);
-hipError_t launch_radix_sort(unsigned long long* k0, uint32_t* v0, unsigned long long* k1,
-                             uint32_t* v1, DevStatus* status, int key_bits, int digit_bits,
-                             SortState* state, uint32_t* lookback, uint32_t n_blocks,
-                             hipStream_t st);
+hipError_t launch_tile_sort(unsigned long long* comp, const uint32_t* tile_counts,
+                            const uint32_t* tile_end, const DevStatus* status,
+                            unsigned long long* keys_out, uint32_t* vals_out, uint32_t* ranges,
+                            uint32_t n_tiles, int digit_bits, int rec_bits, hipStream_t st);
 hipError_t launch_raster_fwd(int tw, int th, int batch, uint32_t persistent_blocks,
                              uint32_t* work, const float* records, const uint32_t* values,
                              const uint32_t* ranges, const DevView* views, int n_views,
@@ -183,29 +181,25 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.digit_bits = tu.digit_bits;
   const int tile_bits = n_tiles > 1 ? ceil_log2_u64(n_tiles) : 0;
   l.pub.key_bits = 32 + tile_bits;
-  l.n_passes = (l.pub.key_bits + tu.digit_bits - 1) / tu.digit_bits;
+  l.rec_bits = n_rec > 1 ? ceil_log2_u64(n_rec) : 1;
   const uint64_t cap = uint64_t(tu.pair_capacity);
-  l.n_sort_blocks = int64_t((cap + kSortTile - 1) / kSortTile);
   l.n_prims = int64_t(n_prims);
-  const uint64_t scan_n = n_rec > n_prims ? n_rec : n_prims;
-  const uint64_t rec_scan_tiles = (scan_n + kScanTile - 1) / kScanTile;
-  const uint64_t lookback_words = uint64_t(l.n_passes) * uint64_t(l.n_sort_blocks) * 256;
-  l.n_scan_blocks = int64_t(rec_scan_tiles);
+  // the scans run over the tile counts and over the primitives' live flags
+  const uint64_t scan_n = n_tiles > n_prims ? n_tiles : n_prims;
+  l.n_scan_blocks = int64_t((scan_n + kScanTile - 1) / kScanTile);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) { const uint64_t o = off; off = align256(off + bytes); return o; };
   l.pub.off_status = take(sizeof(DevStatus));
   l.off_views = take(sizeof(DevView) * uint64_t(f->n_views > 0 ? f->n_views : 1));
   l.off_scenes = take(sizeof(DevScene) * uint64_t(f->n_scenes > 0 ? f->n_scenes : 1));
   l.pub.off_records = take(uint64_t(kRecFloats) * 4 * n_rec);
-  l.off_counts = take(4 * n_rec);
-  l.off_offsets = take(4 * scan_n);
+  l.off_tile_counts = take(4 * n_tiles);
+  l.off_tile_cursor = take(4 * n_tiles);
+  l.off_offsets = take(4 * n_prims);
   l.off_blocksums = take(4 * uint64_t(l.n_scan_blocks + 1));
   l.off_keys0 = take(8 * cap);
-  l.off_keys_alt = take(8 * cap);
+  l.off_comp = take(8 * cap);
   l.off_values0 = take(4 * cap);
-  l.off_values_alt = take(4 * cap);
-  l.off_hist = take(4 * lookback_words);
-  l.off_sort_state = take(sizeof(SortState));
   l.pub.off_ranges = take(8 * n_tiles);
   l.pub.off_ncontrib = take(4 * n_pix);
   l.pub.off_grad2d = take(uint64_t(kGradFloats) * 4 * n_rec);
@@ -215,9 +209,8 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.off_live_count = take(8 * uint64_t(f->n_scenes > 0 ? f->n_scenes : 1));
   l.off_grad_compact = take(4 * n_grad_compact);
   l.pub.bytes = off;
-  const bool odd = (l.n_passes & 1) != 0;
-  l.pub.off_keys = odd ? l.off_keys_alt : l.off_keys0;
-  l.pub.off_values = odd ? l.off_values_alt : l.off_values0;
+  l.pub.off_keys = l.off_keys0;
+  l.pub.off_values = l.off_values0;
   return UBS_OK;
 }
 
@@ -309,33 +302,30 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
   DevStatus* status = at<DevStatus>(ws, L.pub.off_status);
   const DevView* views = at<DevView>(ws, L.off_views);
   const float* records = at<float>(ws, L.pub.off_records);
-  uint32_t* counts = at<uint32_t>(ws, L.off_counts);
-  uint32_t* offsets = at<uint32_t>(ws, L.off_offsets);
+  uint32_t* tile_counts = at<uint32_t>(ws, L.off_tile_counts);
+  uint32_t* tile_cursor = at<uint32_t>(ws, L.off_tile_cursor);
   uint32_t* sums = at<uint32_t>(ws, L.off_blocksums);
   const uint32_t n_rec = uint32_t(L.pub.n_records);
+  const uint32_t n_tiles = uint32_t(L.pub.n_tiles);
   const unsigned long long cap = (unsigned long long)L.pub.pair_capacity;
-  auto* k0 = at<unsigned long long>(ws, L.off_keys0);
-  auto* k1 = at<unsigned long long>(ws, L.off_keys_alt);
-  auto* v0 = at<uint32_t>(ws, L.off_values0);
-  auto* v1 = at<uint32_t>(ws, L.off_values_alt);
+  auto* comp = at<unsigned long long>(ws, L.off_comp);
   stage_mark(frame, UBS_STAGE_BIN_COUNT, 0, s);
-  UBS_HIP(launch_bin_count(records, views, frame->n_views, n_rec, counts, s));
+  UBS_HIP(launch_fill_u32(tile_counts, n_tiles, 0u, s));
+  UBS_HIP(launch_bin_count(records, views, frame->n_views, n_rec, tile_counts, s));
   stage_mark(frame, UBS_STAGE_BIN_COUNT, 1, s);
   stage_mark(frame, UBS_STAGE_SCAN, 0, s);
-  UBS_HIP(launch_scan(counts, n_rec, sums, offsets, status, cap, s, nullptr));
+  // segment starts of the tiles; the total sets pairs_needed and overflow
+  UBS_HIP(launch_scan(tile_counts, n_tiles, sums, tile_cursor, status, cap, s, nullptr));
   stage_mark(frame, UBS_STAGE_SCAN, 1, s);
   stage_mark(frame, UBS_STAGE_BIN_EMIT, 0, s);
-  UBS_HIP(launch_bin_emit(records, views, frame->n_views, n_rec, offsets, status, k0, v0, s));
+  UBS_HIP(launch_bin_emit(records, views, frame->n_views, n_rec, tile_cursor, status, comp, s));
   stage_mark(frame, UBS_STAGE_BIN_EMIT, 1, s);
   stage_mark(frame, UBS_STAGE_SORT, 0, s);
-  UBS_HIP(launch_radix_sort(k0, v0, k1, v1, status, L.pub.key_bits, L.digit_bits,
-                            at<SortState>(ws, L.off_sort_state), at<uint32_t>(ws, L.off_hist),
-                            uint32_t(L.n_sort_blocks), s));
+  UBS_HIP(launch_tile_sort(comp, tile_counts, tile_cursor, status,
+                           at<unsigned long long>(ws, L.pub.off_keys),
+                           at<uint32_t>(ws, L.pub.off_values), at<uint32_t>(ws, L.pub.off_ranges),
+                           n_tiles, L.digit_bits, L.rec_bits, s));
   stage_mark(frame, UBS_STAGE_SORT, 1, s);
-  stage_mark(frame, UBS_STAGE_RANGES, 0, s);
-  UBS_HIP(launch_ranges(at<unsigned long long>(ws, L.pub.off_keys), status,
-                        at<uint32_t>(ws, L.pub.off_ranges), size_t(L.pub.n_tiles), cap, s));
-  stage_mark(frame, UBS_STAGE_RANGES, 1, s);
   return UBS_OK;
 }
 

@@ -1,5 +1,7 @@
-// Tile binning: per-record tile counts, exclusive scan, key/value emission,
-// per-tile ranges.
+// Tile binning: per-tile pair counts, and emission of every (tile, record)
+// pair into its tile's segment (the segments come from an exclusive scan of
+// the counts; the order inside a segment is fixed afterwards by
+// tile_sort.hip).
 //
 // A record overlaps a tile iff the minimum of its quadratic form
 // r(p) = a dx^2 + 2 b dx dy + c dy^2 over the rectangle spanned by the
@@ -149,20 +151,24 @@ __device__ __forceinline__ BinRec load_bin_rec(const float* __restrict__ records
   return b;
 }
 
+__device__ __forceinline__ uint32_t global_tile(const DevView& V, int tx, int ty) {
+  return V.tile_base + uint32_t(ty * V.tiles_x + tx);
+}
+
+// One atomic increment of tile_counts per (tile, record) pair.
 __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict__ records,
                                                         const DevView* __restrict__ views,
                                                         int n_views, uint32_t n_records,
-                                                        uint32_t* __restrict__ counts) {
+                                                        uint32_t* __restrict__ tile_counts) {
   const uint32_t rec = blockIdx.x * 256u + threadIdx.x;
   const bool active = rec < n_records;
   const int lane = threadIdx.x & 63;
   const BinRec b = load_bin_rec(records, views, n_views, rec, active);
-  uint32_t cnt = 0;
   if (b.n_cand > 0 && b.n_cand <= kSmallBox) {
     const DevView& V = views[b.view];
     for (int ty = b.box.ty0; ty <= b.box.ty1; ++ty)
       for (int tx = b.box.tx0; tx <= b.box.tx1; ++tx)
-        cnt += record_hits_tile(b.r0, b.r1, V, tx, ty) ? 1u : 0u;
+        if (record_hits_tile(b.r0, b.r1, V, tx, ty)) atomicAdd(&tile_counts[global_tile(V, tx, ty)], 1u);
   }
   unsigned long long big = __ballot(b.n_cand > kSmallBox);
   while (big) {
@@ -171,72 +177,53 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict_
     const BinRec o = bcast_rec(b, src);
     const DevView& V = views[o.view];
     const int bw = o.box.tx1 - o.box.tx0 + 1;
-    uint32_t total = 0;
     for (int c0 = 0; c0 < o.n_cand; c0 += 64) {
       const int c = c0 + lane;
-      bool hit = false;
-      if (c < o.n_cand)
-        hit = record_hits_tile(o.r0, o.r1, V, o.box.tx0 + c % bw, o.box.ty0 + c / bw);
-      total += uint32_t(__popcll(__ballot(hit)));
+      if (c < o.n_cand) {
+        const int tx = o.box.tx0 + c % bw, ty = o.box.ty0 + c / bw;
+        if (record_hits_tile(o.r0, o.r1, V, tx, ty)) atomicAdd(&tile_counts[global_tile(V, tx, ty)], 1u);
+      }
     }
-    if (lane == src) cnt = total;
   }
-  if (active) counts[rec] = cnt;
 }
 
+// Appends (depth bits << 32 | record) of every pair to its tile's segment;
+// tile_cursor starts at each segment's first slot and ends one past its last.
 __global__ void __launch_bounds__(256) bin_emit_kernel(const float* __restrict__ records,
                                                        const DevView* __restrict__ views,
                                                        int n_views, uint32_t n_records,
-                                                       const uint32_t* __restrict__ offsets,
+                                                       uint32_t* __restrict__ tile_cursor,
                                                        const DevStatus* __restrict__ status,
-                                                       unsigned long long* __restrict__ keys,
-                                                       uint32_t* __restrict__ values) {
+                                                       unsigned long long* __restrict__ comp) {
   if (status->overflow) return;
   const uint32_t rec = blockIdx.x * 256u + threadIdx.x;
   const bool active = rec < n_records;
   const int lane = threadIdx.x & 63;
   const BinRec b = load_bin_rec(records, views, n_views, rec, active);
-  const uint32_t my_off = active ? offsets[rec] : 0u;
   if (b.n_cand > 0 && b.n_cand <= kSmallBox) {
     const DevView& V = views[b.view];
-    const unsigned long long dbits = __float_as_uint(b.depth);
-    uint32_t pos = my_off;
+    const unsigned long long key = ((unsigned long long)__float_as_uint(b.depth) << 32) | rec;
     for (int ty = b.box.ty0; ty <= b.box.ty1; ++ty)
-      for (int tx = b.box.tx0; tx <= b.box.tx1; ++tx) {
-        if (record_hits_tile(b.r0, b.r1, V, tx, ty)) {
-          const unsigned long long tile =
-              (unsigned long long)V.tile_base + (unsigned long long)(ty * V.tiles_x + tx);
-          keys[pos] = (tile << 32) | dbits;
-          values[pos] = rec;
-          ++pos;
-        }
-      }
+      for (int tx = b.box.tx0; tx <= b.box.tx1; ++tx)
+        if (record_hits_tile(b.r0, b.r1, V, tx, ty))
+          comp[atomicAdd(&tile_cursor[global_tile(V, tx, ty)], 1u)] = key;
   }
-  const unsigned long long lt_mask = (1ull << lane) - 1ull;
   unsigned long long big = __ballot(b.n_cand > kSmallBox);
   while (big) {
     const int src = __ffsll((long long)big) - 1;
     big &= big - 1ull;
     const BinRec o = bcast_rec(b, src);
     const uint32_t orec = uint32_t(bcast_i(int(rec), src));
-    uint32_t pos = uint32_t(bcast_i(int(my_off), src));
     const DevView& V = views[o.view];
-    const unsigned long long dbits = __float_as_uint(o.depth);
+    const unsigned long long key = ((unsigned long long)__float_as_uint(o.depth) << 32) | orec;
     const int bw = o.box.tx1 - o.box.tx0 + 1;
     for (int c0 = 0; c0 < o.n_cand; c0 += 64) {
       const int c = c0 + lane;
-      const int tx = o.box.tx0 + c % bw, ty = o.box.ty0 + c / bw;
-      bool hit = false;
-      if (c < o.n_cand) hit = record_hits_tile(o.r0, o.r1, V, tx, ty);
-      const unsigned long long m = __ballot(hit);
-      if (hit) {
-        const uint32_t p = pos + uint32_t(__popcll(m & lt_mask));
-        const unsigned long long tile =
-            (unsigned long long)V.tile_base + (unsigned long long)(ty * V.tiles_x + tx);
-        keys[p] = (tile << 32) | dbits;
-        values[p] = orec;
+      if (c < o.n_cand) {
+        const int tx = o.box.tx0 + c % bw, ty = o.box.ty0 + c / bw;
+        if (record_hits_tile(o.r0, o.r1, V, tx, ty))
+          comp[atomicAdd(&tile_cursor[global_tile(V, tx, ty)], 1u)] = key;
       }
-      pos += uint32_t(__popcll(m));
     }
   }
 }
@@ -325,34 +312,20 @@ __global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(
   }
 }
 
-// ---------------------------------------------------------------------------
-// Per-tile ranges over the sorted keys.
-// ---------------------------------------------------------------------------
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, size_t n, uint32_t v) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t k = i; k < n; k += stride) p[k] = v;
 }
 
-__global__ void __launch_bounds__(256) ranges_kernel(const unsigned long long* __restrict__ keys,
-                                                     const DevStatus* __restrict__ status,
-                                                     uint32_t* __restrict__ ranges) {
-  const unsigned long long K = status->overflow ? 0ull : status->pairs_needed;
-  const size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
-  if (i >= K) return;
-  const uint32_t tile = uint32_t(keys[i] >> 32);
-  if (i == 0 || uint32_t(keys[i - 1] >> 32) != tile) ranges[2 * size_t(tile)] = uint32_t(i);
-  if (i + 1 == K || uint32_t(keys[i + 1] >> 32) != tile) ranges[2 * size_t(tile) + 1] = uint32_t(i + 1);
-}
-
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
-                            uint32_t n_records, uint32_t* counts, hipStream_t st) {
+                            uint32_t n_records, uint32_t* tile_counts, hipStream_t st) {
   if (n_records == 0) return hipSuccess;
   hipLaunchKernelGGL(bin_count_kernel, dim3((n_records + 255) / 256), dim3(256), 0, st, records,
-                     views, n_views, n_records, counts);
+                     views, n_views, n_records, tile_counts);
   return hipGetLastError();
 }
 
@@ -372,11 +345,11 @@ hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint
 }
 
 hipError_t launch_bin_emit(const float* records, const DevView* views, int n_views,
-                           uint32_t n_records, const uint32_t* offsets, const DevStatus* status,
-                           unsigned long long* keys, uint32_t* values, hipStream_t st) {
+                           uint32_t n_records, uint32_t* tile_cursor, const DevStatus* status,
+                           unsigned long long* comp, hipStream_t st) {
   if (n_records == 0) return hipSuccess;
   hipLaunchKernelGGL(bin_emit_kernel, dim3((n_records + 255) / 256), dim3(256), 0, st, records,
-                     views, n_views, n_records, offsets, status, keys, values);
+                     views, n_views, n_records, tile_cursor, status, comp);
   return hipGetLastError();
 }
 
@@ -400,16 +373,6 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st) {
   size_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(fill_u32_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, p, n, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_ranges(const unsigned long long* keys, const DevStatus* status, uint32_t* ranges,
-                         size_t n_tiles, unsigned long long capacity, hipStream_t st) {
-  hipError_t e = launch_fill_u32(ranges, 2 * n_tiles, 0u, st);
-  if (e != hipSuccess) return e;
-  if (capacity == 0) return hipSuccess;
-  hipLaunchKernelGGL(ranges_kernel, dim3(unsigned((capacity + 255) / 256)), dim3(256), 0, st, keys,
-                     status, ranges);
   return hipGetLastError();
 }
 

@@ -1,0 +1,198 @@
+// Per-tile ordering of the (tile, record) pairs.
+//
+// Binning counts the pairs of every tile (one atomic per pair), an exclusive
+// scan of those counts gives every tile a contiguous segment, and emission
+// appends the 64-bit key (depth bits << 32 | record) of each pair to its
+// tile's segment through a per-tile cursor, in no particular order.  The
+// key is unique within a tile (a record meets a tile at most once), so
+// sorting each segment by it yields exactly the order of a stable sort of
+// (tile, depth) keys emitted in record order: depth first, equal depths in
+// record order.
+//
+// tile_sort_kernel: one workgroup per tile (grid-stride over tiles).
+//   n <= 256          rank sort: each key's position is the number of
+//                     smaller keys in the segment (LDS broadcast reads);
+//   n <= kLdsSortMax  bitonic sort in LDS, padded to a power of two;
+//   larger            LSD radix sort of the segment in global memory by the
+//                     workgroup alone (each wavefront owns a contiguous
+//                     quarter, so the scatter is stable without barriers),
+//                     ping-ponging with the segment's slice of the output
+//                     key buffer; digits that are constant over the segment
+//                     are skipped.
+// It also writes the tile's [start, end) range (empty after an overflow).
+#include "ubs_internal.hpp"
+
+namespace ubs {
+
+constexpr int kTileSortThreads = 256;
+constexpr int kLdsSortMax = 4096;   // keys held in LDS (32 KiB)
+
+__device__ __forceinline__ void write_sorted(unsigned long long key, uint32_t tile, size_t pos,
+                                             unsigned long long* __restrict__ keys_out,
+                                             uint32_t* __restrict__ vals_out) {
+  keys_out[pos] = ((unsigned long long)tile << 32) | (key >> 32);
+  vals_out[pos] = uint32_t(key);
+}
+
+// Exclusive scan over 256 threads (4 waves); lds4 holds 4 words.
+__device__ __forceinline__ uint32_t wg_exclusive_scan(uint32_t v, uint32_t* lds4) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds4[wave] = x;
+  __syncthreads();
+  uint32_t wb = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) wb += w < wave ? lds4[w] : 0u;
+  __syncthreads();
+  return wb + x - v;
+}
+
+// LSD radix sort of seg[0, n) by one workgroup, using alt[0, n) as the second
+// buffer.  Sorts the bits [0, rec_bits) and [32, 64).  Returns the buffer
+// holding the result.
+__device__ unsigned long long* wg_radix_sort(unsigned long long* seg, unsigned long long* alt,
+                                             uint32_t n, int digit_bits, int rec_bits,
+                                             uint32_t (*hist)[256], uint32_t* lds4,
+                                             uint32_t* s_flag) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  const uint32_t R = 1u << digit_bits, mask = R - 1u;
+  const uint32_t quarter = (n + 3u) / 4u;
+  const uint32_t q0 = min(n, uint32_t(wave) * quarter), q1 = min(n, q0 + quarter);
+  unsigned long long* src = seg;
+  unsigned long long* dst = alt;
+  for (int shift = 0; shift < 64; shift += digit_bits) {
+    if (shift >= rec_bits && shift + digit_bits <= 32) continue;   // always zero
+    for (uint32_t d = threadIdx.x; d < 4u * 256u; d += kTileSortThreads) (&hist[0][0])[d] = 0u;
+    if (threadIdx.x == 0) *s_flag = 0u;
+    __syncthreads();
+    for (uint32_t i = q0 + lane; i < q1; i += 64)
+      atomicAdd(&hist[wave][uint32_t(src[i] >> shift) & mask], 1u);
+    __syncthreads();
+    const uint32_t d = threadIdx.x;
+    uint32_t c[4] = {0u, 0u, 0u, 0u}, tot = 0u;
+    if (d < R) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) { c[w] = hist[w][d]; tot += c[w]; }
+      if (tot == n) *s_flag = 1u;   // one digit value only: the pass is the identity
+    }
+    const uint32_t excl = wg_exclusive_scan(d < R ? tot : 0u, lds4);
+    if (d < R) {
+      uint32_t run = excl;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) { hist[w][d] = run; run += c[w]; }
+    }
+    __syncthreads();
+    const bool identity = *s_flag != 0u;
+    __syncthreads();   // every thread has read the flag before the next pass resets it
+    if (identity) continue;
+    // stable scatter of the wave's quarter, 64 keys at a time
+    for (uint32_t b = q0; b < q1; b += 64) {
+      const uint32_t i = b + lane;
+      const bool valid = i < q1;
+      const unsigned long long k = valid ? src[i] : 0ull;
+      const uint32_t dg = uint32_t(k >> shift) & mask;
+      unsigned long long m = __ballot(valid);
+      for (int bit = 0; bit < digit_bits; ++bit) {
+        const bool on = (dg >> bit) & 1u;
+        const unsigned long long bb = __ballot(on);
+        m &= on ? bb : ~bb;
+      }
+      if (valid) {
+        const uint32_t below = uint32_t(__popcll(m & lt_mask));
+        dst[hist[wave][dg] + below] = k;
+        if (below == 0) hist[wave][dg] += uint32_t(__popcll(m));
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    unsigned long long* t = src; src = dst; dst = t;
+  }
+  return src;
+}
+
+__global__ void __launch_bounds__(kTileSortThreads) tile_sort_kernel(
+    unsigned long long* __restrict__ comp, const uint32_t* __restrict__ tile_counts,
+    const uint32_t* __restrict__ tile_end, const DevStatus* __restrict__ status,
+    unsigned long long* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+    uint32_t* __restrict__ ranges, uint32_t n_tiles, int digit_bits, int rec_bits) {
+  __shared__ unsigned long long s_keys[kLdsSortMax];
+  __shared__ uint32_t s_hist[4][256];
+  __shared__ uint32_t s_lds4[4];
+  __shared__ uint32_t s_flag;
+  const bool overflow = status->overflow != 0u;
+  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const uint32_t n = overflow ? 0u : tile_counts[t];
+    const uint32_t end = overflow ? 0u : tile_end[t];
+    const uint32_t start = end - n;
+    if (threadIdx.x == 0) {
+      ranges[2 * size_t(t)] = start;
+      ranges[2 * size_t(t) + 1] = end;
+    }
+    if (n == 0) continue;
+    if (n <= kTileSortThreads) {
+      const uint32_t i = threadIdx.x;
+      const unsigned long long k = i < n ? comp[start + i] : 0ull;
+      if (i < n) s_keys[i] = k;
+      __syncthreads();
+      if (i < n) {
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < n; ++j) rank += s_keys[j] < k ? 1u : 0u;
+        write_sorted(k, t, size_t(start) + rank, keys_out, vals_out);
+      }
+      __syncthreads();
+    } else if (n <= uint32_t(kLdsSortMax)) {
+      uint32_t P = 512;
+      while (P < n) P <<= 1;
+      for (uint32_t i = threadIdx.x; i < P; i += kTileSortThreads)
+        s_keys[i] = i < n ? comp[start + i] : ~0ull;
+      __syncthreads();
+      for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+          for (uint32_t i = threadIdx.x; i < P / 2; i += kTileSortThreads) {
+            const uint32_t lo = 2 * i - (i & (j - 1));
+            const uint32_t hi = lo + j;
+            const unsigned long long a = s_keys[lo], b = s_keys[hi];
+            const bool up = (lo & k) == 0;
+            if ((a > b) == up) {
+              s_keys[lo] = b;
+              s_keys[hi] = a;
+            }
+          }
+          __syncthreads();
+        }
+      }
+      for (uint32_t i = threadIdx.x; i < n; i += kTileSortThreads)
+        write_sorted(s_keys[i], t, size_t(start) + i, keys_out, vals_out);
+      __syncthreads();
+    } else {
+      // the segment's slice of the output key buffer is the second buffer
+      unsigned long long* res = wg_radix_sort(comp + start, keys_out + start, n, digit_bits,
+                                              rec_bits, s_hist, s_lds4, &s_flag);
+      for (uint32_t i = threadIdx.x; i < n; i += kTileSortThreads) {
+        const unsigned long long k = res[i];   // read before the same thread overwrites slot i
+        write_sorted(k, t, size_t(start) + i, keys_out, vals_out);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t launch_tile_sort(unsigned long long* comp, const uint32_t* tile_counts,
+                            const uint32_t* tile_end, const DevStatus* status,
+                            unsigned long long* keys_out, uint32_t* vals_out, uint32_t* ranges,
+                            uint32_t n_tiles, int digit_bits, int rec_bits, hipStream_t st) {
+  if (n_tiles == 0) return hipSuccess;
+  const uint32_t grid = n_tiles < 65536u ? n_tiles : 65536u;
+  hipLaunchKernelGGL(tile_sort_kernel, dim3(grid), dim3(kTileSortThreads), 0, st, comp,
+                     tile_counts, tile_end, status, keys_out, vals_out, ranges, n_tiles,
+                     digit_bits, rec_bits);
+  return hipGetLastError();
+}
+
+}  // namespace ubs

@@ -72,43 +72,33 @@ struct DevStatus {
   uint32_t overflow;
   uint32_t n_nonfinite;
   uint32_t n_visible;
-  uint32_t sort_stalled;     // a radix look-back wait hit its bound
+  uint32_t sort_stalled;     // reserved (no bounded wait in the current kernels), 0
   uint32_t work_counter[3];  // persistent raster queues (fwd, bwd, spare)
   uint32_t _pad[7];
 };
 
-// Radix sort scratch: dynamic tile counters and the digit histograms of
-// every pass.
-constexpr int kSortPassMax = 16;
-struct SortState {
-  uint32_t tile_counter[kSortPassMax];
-  uint32_t hist[kSortPassMax * 256];
-};
 static_assert(sizeof(DevStatus) == sizeof(ubs_status_block), "status block size");
 
 // Full private layout of the workspace (superset of ubs_layout).
 struct Layout {
   ubs_layout pub;
-  uint64_t off_views, off_scenes, off_counts, off_offsets, off_blocksums;
-  uint64_t off_keys_alt, off_values_alt, off_hist, off_sort_state;
-  uint64_t off_keys0, off_values0;  // ping-pong buffer 0
+  uint64_t off_views, off_scenes, off_offsets, off_blocksums;
+  uint64_t off_tile_counts, off_tile_cursor;  // pairs per tile; segment cursors
+  uint64_t off_comp;                 // emitted (depth bits << 32 | record) per tile segment
+  uint64_t off_keys0, off_values0;   // sorted keys and values
   uint64_t off_tfinal_ws;            // final transmittance kept for the adjoint
   uint64_t off_live, off_live_list, off_live_count;  // per-primitive live flags, compacted list, counts
   uint64_t off_grad_compact;         // adjoint output of live primitives, [F][n] per scene
   int64_t n_prims;                   // sum over scenes of primitives
   int64_t n_scan_blocks;
-  int64_t n_sort_blocks;
-  int32_t n_passes, digit_bits;
+  int32_t rec_bits, digit_bits;
   int32_t tile_w, tile_h;
 };
 
-// Scan / sort geometry.
+// Scan geometry.
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;                       // per thread
 constexpr int kScanTile = kScanThreads * kScanItems; // 4096 per block
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 8;                        // per lane
-constexpr int kSortTile = kSortThreads * kSortItems; // 2048 per block
 
 inline int ceil_log2_u64(uint64_t x) {
   int b = 0;

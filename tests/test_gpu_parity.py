@@ -114,12 +114,16 @@ def test_bin_sort_bit_exact_multi_view():
 
 
 @pytest.mark.parametrize("digit_bits", [4, 5, 7, 8])
-def test_sort_digit_widths_agree(digit_bits):
+@pytest.mark.parametrize("n,W,H,ext", [(2000, 300, 200, 30.0),    # short segments: rank sort
+                                       (3000, 64, 48, 40.0),      # 395-519 per tile: bitonic
+                                       (9000, 24, 20, 40.0)])     # 5459 in one tile: radix
+def test_sort_paths_and_digit_widths_agree(digit_bits, n, W, H, ext):
     from paper_2510_03312_amd import Tuning
-    log(f"[bin_sort] digit_bits={digit_bits}")
-    cfg = make_config("cfg0", n=2000, width=300, height=200)
-    recs = make_splat_records(2000, 300, 200, seed=5, max_extent=30.0)
-    sk, sv, rg = bin_reference(recs, [_V(cfg["views"][0], 2000)])
+    log(f"[bin_sort] digit_bits={digit_bits} n={n} {W}x{H}")
+    cfg = make_config("cfg0", n=n, width=W, height=H)
+    recs = make_splat_records(n, W, H, seed=5, max_extent=ext)
+    recs[:50, 11] = recs[50:100, 11]          # exact depth ties
+    sk, sv, rg = bin_reference(recs, [_V(cfg["views"][0], n)])
     from paper_2510_03312_amd import Renderer, SceneRef
     r = Renderer(Tuning(pair_capacity=1 << 18, digit_bits=digit_bits))
     frame = r.make_frame([SceneRef(to_dev(cfg["scenes"][0].params), 3, 0)], cfg["views"])
@@ -127,9 +131,13 @@ def test_sort_digit_widths_agree(digit_bits):
     r.records().copy_(to_dev(recs))
     r.bin_sort(frame)
     K = r.status()["pairs_needed"]
+    assert K == sk.size
+    per_tile = (rg[:, 1] - rg[:, 0]).astype(np.int64)
+    log(f"  pairs {K}, longest segment {per_tile.max()}")
     keys, vals = r.sorted_pairs(K)
     np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint64), sk)
     np.testing.assert_array_equal(vals.cpu().numpy().view(np.uint32), sv)
+    np.testing.assert_array_equal(r.ranges().cpu().numpy().view(np.uint32), rg)
 
 
 # ------------------------------------------------------------------ forward
