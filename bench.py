@@ -20,7 +20,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -100,15 +99,13 @@ def recorded_traffic(workload: str, kernel: str):
 
 def stage_bytes(stage: str, c: dict) -> float:
     """Algorithmic HBM bytes of one launch of a stage."""
-    P, F, R, Pv, K, A, G, npass = (c["P"], c["F"], c["R"], c["Pv"], c["K"], c["A"], c["G"],
-                                   c["passes"])
+    P, F, R, Pv, K, A, G = c["P"], c["F"], c["R"], c["Pv"], c["K"], c["A"], c["G"]
     return {
         "preprocess": 4.0 * F * P + 48.0 * R,
-        "bin_count": 36.0 * R,
-        "scan": 12.0 * R,
-        "bin_emit": 40.0 * R + 12.0 * K,
-        "sort": 24.0 * K * npass,
-        "ranges": 8.0 * K + 8.0 * G,
+        "bin_count": 36.0 * R + 4.0 * K + 4.0 * G,
+        "scan": 12.0 * G,
+        "bin_emit": 36.0 * R + 12.0 * K,
+        "sort": 20.0 * K + 16.0 * G,
         "raster_fwd": 52.0 * K + 20.0 * A + 8.0 * G,
         "grad_clear": 40.0 * R,
         "raster_bwd": 92.0 * K + 32.0 * A + 8.0 * G,
@@ -204,35 +201,46 @@ def cpu_baseline(cfg, rows: int = 24, sub: int = 100_000) -> dict:
 
 
 def timed_steps(gf, steps: int, eager: bool):
-    """Times `steps` frames; returns (ms per step, per-stage mean ms).  With
-    graphs, step k replays a graph captured with stage-event slot k."""
+    """Times `steps` frames; returns ms per step.  Graph replays or plain calls."""
+    import torch
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        gf.step() if eager else gf.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def timed_stages(gf, steps: int):
+    """Per-stage durations (mean ms) of `steps` plain-call frames, from HIP
+    events the library records around each stage on the frame's stream; also
+    returns the ms per step of those frames."""
     import numpy as np
     import torch
     from paper_2510_03312_amd.timing import StageTimer
 
     timer = StageTimer(steps)
     stream = torch.cuda.current_stream()
-    graphs = None if eager else [gf.capture(timer.slot(k)) for k in range(steps)]
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
     for k in range(steps):
-        if eager:
-            timer.attach(gf.frame.c, k)
-            gf.step()
-        else:
-            graphs[k].replay()
+        timer.attach(gf.frame.c, k)
+        gf.step()
     e1.record(stream)
     torch.cuda.synchronize()
     timer.detach(gf.frame.c)
-    ms = e0.elapsed_time(e1) / steps
     stages = {}
     for k in range(steps):
         for s, v in timer.elapsed_ms(k).items():
             stages.setdefault(s, []).append(v)
     timer.close()
-    return ms, {s: float(np.mean(v)) for s, v in stages.items()}
+    return e0.elapsed_time(e1) / steps, {s: float(np.mean(v)) for s, v in stages.items()}
 
 
 def run_single(args, name, desc):
@@ -265,14 +273,18 @@ def run_single(args, name, desc):
     assert not st["overflow"] and not st["sort_stalled"], st
     log(f"[bench] pairs {st['pairs_needed']:,} visible {st['n_visible']:,}; timing {args.steps} steps")
     t_wall = time.perf_counter()
-    ms, stages_ms = timed_steps(gf, args.steps, args.eager)
+    ms = timed_steps(gf, args.steps, args.eager)
     t_wall = time.perf_counter() - t_wall
+    # per-stage kernel durations: the same frame as plain calls with the
+    # library's stage events (kernel durations do not depend on the launch
+    # mode; graph replays only remove the launch gaps between them)
+    log("[bench] per-stage timing")
+    eager_ms, stages_ms = timed_stages(gf, args.steps)
     st = r.status()
     assert not st["overflow"] and not st["sort_stalled"], st
     lay = r.layout
     c = {"P": sc.n, "F": int(sc.params.shape[0]), "R": lay.n_records, "Pv": st["n_visible"],
-         "K": st["pairs_needed"], "A": lay.n_pixels, "G": lay.n_tiles,
-         "passes": math.ceil(lay.key_bits / r.tuning.digit_bits)}
+         "K": st["pairs_needed"], "A": lay.n_pixels, "G": lay.n_tiles}
     dom = max(stages_ms, key=stages_ms.get)
     ach = stage_bytes(dom, c) / (stages_ms[dom] * 1e-3) / 1e9
     frame_bytes = sum(stage_bytes(s, c) for s in stages_ms)
@@ -301,6 +313,7 @@ def run_single(args, name, desc):
         "kernel_sources": kernel_sources_digest(),
         "frame_hbm_frac": round(frame_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
         "stages_ms": {k: round(v, 4) for k, v in stages_ms.items()},
+        "eager_ms_per_step": round(eager_ms, 4),
         "per_primitive_math": "f32" if args.pre_fp32 else "f64",
         "wall_s": round(t_wall, 3),
     }
@@ -335,7 +348,8 @@ def run_batched(args, name, desc):
                         l1_target=target if backward else None, backward=backward)
         for _ in range(args.warmup):
             gf.replay()
-        ms, stages = timed_steps(gf, args.steps, args.eager)
+        ms = timed_steps(gf, args.steps, args.eager)
+        _, stages = timed_stages(gf, max(2, args.steps // 2))
         st = gf.status()
         assert not st["overflow"] and not st["sort_stalled"], st
         batched[mode] = {"views_per_s": round(len(views) * 1000.0 / ms, 2), "ms_per_frame": round(ms, 4),

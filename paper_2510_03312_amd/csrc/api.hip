@@ -19,13 +19,15 @@ hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const 
 hipError_t launch_compact(const uint32_t* flags, const uint32_t* offsets, uint32_t n,
                           uint32_t* list, hipStream_t st);
 hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
-                            uint32_t n_records, uint32_t* tile_counts, hipStream_t st);
+                            uint32_t n_records, uint32_t* tile_counts, uint32_t* hit_mask,
+                            uint32_t* big_list, uint32_t* big_count, hipStream_t st);
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
                        DevStatus* status, unsigned long long capacity, hipStream_t st,
                        unsigned long long* total_out);
 hipError_t launch_bin_emit(const float* records, const DevView* views, int n_views,
-                           uint32_t n_records, uint32_t* tile_cursor, const DevStatus* status,
-                           unsigned long long* comp, hipStream_t st);
+                           uint32_t n_records, const uint32_t* hit_mask, const uint32_t* big_list,
+                           const uint32_t* big_count, uint32_t* tile_cursor,
+                           const DevStatus* status, unsigned long long* comp, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_tile_sort(unsigned long long* comp, const uint32_t* tile_counts,
                             const uint32_t* tile_end, const DevStatus* status,
@@ -74,6 +76,7 @@ __global__ void fill_f32_kernel(float* __restrict__ p, size_t n) {
   for (size_t k = i; k < n; k += stride) p[k] = 0.0f;
 }
 
+// Records a stage event on the call's stream.
 static void stage_mark(const ubs_frame* f, int stage, int end, hipStream_t s) {
   if (f->stage_events) {
     hipEvent_t e = static_cast<hipEvent_t>(f->stage_events[2 * stage + end]);
@@ -193,8 +196,10 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.off_views = take(sizeof(DevView) * uint64_t(f->n_views > 0 ? f->n_views : 1));
   l.off_scenes = take(sizeof(DevScene) * uint64_t(f->n_scenes > 0 ? f->n_scenes : 1));
   l.pub.off_records = take(uint64_t(kRecFloats) * 4 * n_rec);
-  l.off_tile_counts = take(4 * n_tiles);
+  l.off_tile_counts = take(4 * (n_tiles + 1));
   l.off_tile_cursor = take(4 * n_tiles);
+  l.off_hit_mask = take(4 * n_rec);
+  l.off_big_list = take(4 * n_rec);
   l.off_offsets = take(4 * n_prims);
   l.off_blocksums = take(4 * uint64_t(l.n_scan_blocks + 1));
   l.off_keys0 = take(8 * cap);
@@ -310,15 +315,21 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
   const unsigned long long cap = (unsigned long long)L.pub.pair_capacity;
   auto* comp = at<unsigned long long>(ws, L.off_comp);
   stage_mark(frame, UBS_STAGE_BIN_COUNT, 0, s);
-  UBS_HIP(launch_fill_u32(tile_counts, n_tiles, 0u, s));
-  UBS_HIP(launch_bin_count(records, views, frame->n_views, n_rec, tile_counts, s));
+  // the word after the tile counts counts the records binned by workgroups
+  uint32_t* big_count = tile_counts + n_tiles;
+  uint32_t* big_list = at<uint32_t>(ws, L.off_big_list);
+  UBS_HIP(launch_fill_u32(tile_counts, size_t(n_tiles) + 1, 0u, s));
+  uint32_t* hit_mask = at<uint32_t>(ws, L.off_hit_mask);
+  UBS_HIP(launch_bin_count(records, views, frame->n_views, n_rec, tile_counts, hit_mask, big_list,
+                           big_count, s));
   stage_mark(frame, UBS_STAGE_BIN_COUNT, 1, s);
   stage_mark(frame, UBS_STAGE_SCAN, 0, s);
   // segment starts of the tiles; the total sets pairs_needed and overflow
   UBS_HIP(launch_scan(tile_counts, n_tiles, sums, tile_cursor, status, cap, s, nullptr));
   stage_mark(frame, UBS_STAGE_SCAN, 1, s);
   stage_mark(frame, UBS_STAGE_BIN_EMIT, 0, s);
-  UBS_HIP(launch_bin_emit(records, views, frame->n_views, n_rec, tile_cursor, status, comp, s));
+  UBS_HIP(launch_bin_emit(records, views, frame->n_views, n_rec, hit_mask, big_list, big_count,
+                          tile_cursor, status, comp, s));
   stage_mark(frame, UBS_STAGE_BIN_EMIT, 1, s);
   stage_mark(frame, UBS_STAGE_SORT, 0, s);
   UBS_HIP(launch_tile_sort(comp, tile_counts, tile_cursor, status,

@@ -155,74 +155,199 @@ __device__ __forceinline__ uint32_t global_tile(const DevView& V, int tx, int ty
   return V.tile_base + uint32_t(ty * V.tiles_x + tx);
 }
 
-// One atomic increment of tile_counts per (tile, record) pair.
+// Each wavefront takes kBinRecPerWave consecutive records and first packs the
+// indices of the live ones (rho > 0) into a per-wave LDS list, so that its
+// lanes then work only on live records (after culling, typically a fifth of
+// them).
+constexpr int kBinRecPerWave = 256;
+constexpr int kBinWaves = 4;   // 256-thread workgroups
+
+__device__ __forceinline__ uint32_t gather_live(const float* __restrict__ records,
+                                                uint32_t n_records, uint32_t* __restrict__ list) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t wave_global = blockIdx.x * kBinWaves + (threadIdx.x >> 6);
+  const uint32_t base = wave_global * kBinRecPerWave;
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int m = 0; m < kBinRecPerWave / 64; ++m) {
+    const uint32_t rec = base + uint32_t(m * 64 + lane);
+    const bool vis = rec < n_records && records[size_t(rec) * kRecFloats + 5] > 0.0f;
+    const unsigned long long mask = __ballot(vis);
+    if (vis) list[cnt + uint32_t(__popcll(mask & lt_mask))] = rec;
+    cnt += uint32_t(__popcll(mask));
+  }
+  __builtin_amdgcn_wave_barrier();
+  return cnt;
+}
+
+// Position of flat index f in a wavefront's work list: the last slot j whose
+// exclusive prefix excl[j] is <= f (slots holding no work share their
+// successor's prefix, so the last such slot is the one f belongs to).
+__device__ __forceinline__ int owner_slot(const uint32_t* excl, uint32_t f) {
+  int j = 0;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1)
+    if (excl[j + step] <= f) j += step;
+  return j;
+}
+
+// Inclusive sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(v, o, 64);
+    if (lane >= o) v += y;
+  }
+  return v;
+}
+
+// One atomic increment of tile_counts per (tile, record) pair.  Records with
+// at most kSmallBox candidate tiles are binned 64 at a time by the whole
+// wavefront: their candidates form one flat list (record order, row-major
+// candidates) that the lanes take in turns, so a wavefront runs as many
+// rounds of tile tests as it has candidates / 64 rather than as its largest
+// record has candidates.  The hits of each record (bit k: candidate k) are
+// kept as a mask for the emission.  Larger records are appended to
+// big_list and binned by bin_big_kernel, a workgroup per record.
 __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict__ records,
                                                         const DevView* __restrict__ views,
                                                         int n_views, uint32_t n_records,
-                                                        uint32_t* __restrict__ tile_counts) {
-  const uint32_t rec = blockIdx.x * 256u + threadIdx.x;
-  const bool active = rec < n_records;
-  const int lane = threadIdx.x & 63;
-  const BinRec b = load_bin_rec(records, views, n_views, rec, active);
-  if (b.n_cand > 0 && b.n_cand <= kSmallBox) {
-    const DevView& V = views[b.view];
-    for (int ty = b.box.ty0; ty <= b.box.ty1; ++ty)
-      for (int tx = b.box.tx0; tx <= b.box.tx1; ++tx)
-        if (record_hits_tile(b.r0, b.r1, V, tx, ty)) atomicAdd(&tile_counts[global_tile(V, tx, ty)], 1u);
-  }
-  unsigned long long big = __ballot(b.n_cand > kSmallBox);
-  while (big) {
-    const int src = __ffsll((long long)big) - 1;
-    big &= big - 1ull;
-    const BinRec o = bcast_rec(b, src);
-    const DevView& V = views[o.view];
-    const int bw = o.box.tx1 - o.box.tx0 + 1;
-    for (int c0 = 0; c0 < o.n_cand; c0 += 64) {
-      const int c = c0 + lane;
-      if (c < o.n_cand) {
-        const int tx = o.box.tx0 + c % bw, ty = o.box.ty0 + c / bw;
-        if (record_hits_tile(o.r0, o.r1, V, tx, ty)) atomicAdd(&tile_counts[global_tile(V, tx, ty)], 1u);
+                                                        uint32_t* __restrict__ tile_counts,
+                                                        uint32_t* __restrict__ hit_mask,
+                                                        uint32_t* __restrict__ big_list,
+                                                        uint32_t* __restrict__ big_count) {
+  __shared__ uint32_t s_list[kBinWaves][kBinRecPerWave];
+  __shared__ uint32_t s_excl[kBinWaves][65];
+  __shared__ float4 s_r0[kBinWaves][64];
+  __shared__ float2 s_r1[kBinWaves][64];
+  __shared__ int4 s_box[kBinWaves][64];     // tx0, ty0, box width, view
+  __shared__ uint32_t s_mask[kBinWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  uint32_t* list = s_list[w];
+  const uint32_t cnt = gather_live(records, n_records, list);
+  for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
+    const bool active = c0 + lane < cnt;
+    const uint32_t rec = active ? list[c0 + lane] : 0u;
+    const BinRec b = load_bin_rec(records, views, n_views, rec, active);
+    const bool small = b.n_cand > 0 && b.n_cand <= kSmallBox;
+    const uint32_t nc = small ? uint32_t(b.n_cand) : 0u;
+    const uint32_t incl = wave_inclusive_sum(nc);
+    const uint32_t total = uint32_t(__shfl(int(incl), 63, 64));
+    s_excl[w][lane] = incl - nc;
+    if (lane == 0) s_excl[w][64] = 0xffffffffu;
+    s_r0[w][lane] = b.r0;
+    s_r1[w][lane] = make_float2(b.r1.x, b.r1.y);
+    s_box[w][lane] = make_int4(b.box.tx0, b.box.ty0, b.box.tx1 - b.box.tx0 + 1, b.view);
+    s_mask[w][lane] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t f = lane; f < total; f += 64) {
+      const int j = owner_slot(s_excl[w], f);
+      const int k = int(f - s_excl[w][j]);
+      const int4 bx = s_box[w][j];
+      const DevView& V = views[bx.w];
+      const int tx = bx.x + k % bx.z, ty = bx.y + k / bx.z;
+      const float2 r1 = s_r1[w][j];
+      if (record_hits_tile(s_r0[w][j], make_float4(r1.x, r1.y, 0.f, 0.f), V, tx, ty)) {
+        atomicAdd(&tile_counts[global_tile(V, tx, ty)], 1u);
+        atomicOr(&s_mask[w][j], 1u << k);
       }
     }
+    __builtin_amdgcn_wave_barrier();
+    if (small) hit_mask[rec] = s_mask[w][lane];
+    const bool big = b.n_cand > kSmallBox;
+    const unsigned long long bm = __ballot(big);
+    if (bm) {
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(big_count, uint32_t(__popcll(bm)));
+      base = uint32_t(__shfl(int(base), 0, 64));
+      if (big) big_list[base + uint32_t(__popcll(bm & lt_mask))] = rec;
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
-// Appends (depth bits << 32 | record) of every pair to its tile's segment;
-// tile_cursor starts at each segment's first slot and ends one past its last.
+// Appends (depth bits << 32 | record) of every pair of the records with at
+// most kSmallBox candidates to its tile's segment, replaying bin_count's hit
+// masks as one flat list of hits per 64 records (one round of independent
+// cursor atomics per 64 hits); tile_cursor starts at each segment's first
+// slot and ends one past its last.
 __global__ void __launch_bounds__(256) bin_emit_kernel(const float* __restrict__ records,
                                                        const DevView* __restrict__ views,
                                                        int n_views, uint32_t n_records,
+                                                       const uint32_t* __restrict__ hit_mask,
                                                        uint32_t* __restrict__ tile_cursor,
                                                        const DevStatus* __restrict__ status,
                                                        unsigned long long* __restrict__ comp) {
   if (status->overflow) return;
-  const uint32_t rec = blockIdx.x * 256u + threadIdx.x;
-  const bool active = rec < n_records;
-  const int lane = threadIdx.x & 63;
-  const BinRec b = load_bin_rec(records, views, n_views, rec, active);
-  if (b.n_cand > 0 && b.n_cand <= kSmallBox) {
-    const DevView& V = views[b.view];
-    const unsigned long long key = ((unsigned long long)__float_as_uint(b.depth) << 32) | rec;
-    for (int ty = b.box.ty0; ty <= b.box.ty1; ++ty)
-      for (int tx = b.box.tx0; tx <= b.box.tx1; ++tx)
-        if (record_hits_tile(b.r0, b.r1, V, tx, ty))
-          comp[atomicAdd(&tile_cursor[global_tile(V, tx, ty)], 1u)] = key;
+  __shared__ uint32_t s_list[kBinWaves][kBinRecPerWave];
+  __shared__ uint32_t s_excl[kBinWaves][65];
+  __shared__ unsigned long long s_key[kBinWaves][64];
+  __shared__ int4 s_box[kBinWaves][64];     // tx0, ty0, box width, view
+  __shared__ uint32_t s_bits[kBinWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t* list = s_list[w];
+  const uint32_t cnt = gather_live(records, n_records, list);
+  for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
+    const bool active = c0 + lane < cnt;
+    const uint32_t rec = active ? list[c0 + lane] : 0u;
+    const BinRec b = load_bin_rec(records, views, n_views, rec, active);
+    const bool small = b.n_cand > 0 && b.n_cand <= kSmallBox;
+    const uint32_t bits = small ? hit_mask[rec] : 0u;
+    const uint32_t nh = uint32_t(__popc(bits));
+    const uint32_t incl = wave_inclusive_sum(nh);
+    const uint32_t total = uint32_t(__shfl(int(incl), 63, 64));
+    s_excl[w][lane] = incl - nh;
+    if (lane == 0) s_excl[w][64] = 0xffffffffu;
+    s_key[w][lane] = ((unsigned long long)__float_as_uint(b.depth) << 32) | rec;
+    s_box[w][lane] = make_int4(b.box.tx0, b.box.ty0, b.box.tx1 - b.box.tx0 + 1, b.view);
+    s_bits[w][lane] = bits;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t f = lane; f < total; f += 64) {
+      const int j = owner_slot(s_excl[w], f);
+      uint32_t m = f - s_excl[w][j];
+      uint32_t bb = s_bits[w][j];
+      while (m--) bb &= bb - 1u;           // drop the hits before the m-th
+      const int k = __ffs(int(bb)) - 1;
+      const int4 bx = s_box[w][j];
+      const DevView& V = views[bx.w];
+      const int tx = bx.x + k % bx.z, ty = bx.y + k / bx.z;
+      comp[atomicAdd(&tile_cursor[global_tile(V, tx, ty)], 1u)] = s_key[w][j];
+    }
+    __builtin_amdgcn_wave_barrier();
   }
-  unsigned long long big = __ballot(b.n_cand > kSmallBox);
-  while (big) {
-    const int src = __ffsll((long long)big) - 1;
-    big &= big - 1ull;
-    const BinRec o = bcast_rec(b, src);
-    const uint32_t orec = uint32_t(bcast_i(int(rec), src));
+}
+
+// Records with more than kSmallBox candidate tiles: a workgroup per record
+// (grid-stride over big_list), its threads testing consecutive candidates.
+// EMIT = false counts the hits into tile_counts, EMIT = true appends them.
+template <bool EMIT>
+__global__ void __launch_bounds__(256) bin_big_kernel(const float* __restrict__ records,
+                                                      const DevView* __restrict__ views,
+                                                      int n_views,
+                                                      const uint32_t* __restrict__ big_list,
+                                                      const uint32_t* __restrict__ big_count,
+                                                      uint32_t* __restrict__ tile_counts,
+                                                      uint32_t* __restrict__ tile_cursor,
+                                                      const DevStatus* __restrict__ status,
+                                                      unsigned long long* __restrict__ comp) {
+  if (EMIT && status->overflow) return;
+  const uint32_t nb = *big_count;
+  for (uint32_t bi = blockIdx.x; bi < nb; bi += gridDim.x) {
+    const uint32_t rec = big_list[bi];
+    const BinRec o = load_bin_rec(records, views, n_views, rec, true);
     const DevView& V = views[o.view];
-    const unsigned long long key = ((unsigned long long)__float_as_uint(o.depth) << 32) | orec;
     const int bw = o.box.tx1 - o.box.tx0 + 1;
-    for (int c0 = 0; c0 < o.n_cand; c0 += 64) {
-      const int c = c0 + lane;
-      if (c < o.n_cand) {
-        const int tx = o.box.tx0 + c % bw, ty = o.box.ty0 + c / bw;
-        if (record_hits_tile(o.r0, o.r1, V, tx, ty))
+    const unsigned long long key = ((unsigned long long)__float_as_uint(o.depth) << 32) | rec;
+    for (int k = int(threadIdx.x); k < o.n_cand; k += 256) {
+      const int tx = o.box.tx0 + k % bw, ty = o.box.ty0 + k / bw;
+      if (record_hits_tile(o.r0, o.r1, V, tx, ty)) {
+        if (EMIT)
           comp[atomicAdd(&tile_cursor[global_tile(V, tx, ty)], 1u)] = key;
+        else
+          atomicAdd(&tile_counts[global_tile(V, tx, ty)], 1u);
       }
     }
   }
@@ -321,11 +446,22 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, size_t n, uint32_t v) 
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+static unsigned bin_blocks(uint32_t n_records) {
+  constexpr uint32_t per_block = uint32_t(kBinWaves * kBinRecPerWave);
+  return unsigned((uint64_t(n_records) + per_block - 1) / per_block);
+}
+
+constexpr unsigned kBigBlocks = 1024;
+
+// tile_counts and *big_count must be zero.
 hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
-                            uint32_t n_records, uint32_t* tile_counts, hipStream_t st) {
+                            uint32_t n_records, uint32_t* tile_counts, uint32_t* hit_mask,
+                            uint32_t* big_list, uint32_t* big_count, hipStream_t st) {
   if (n_records == 0) return hipSuccess;
-  hipLaunchKernelGGL(bin_count_kernel, dim3((n_records + 255) / 256), dim3(256), 0, st, records,
-                     views, n_views, n_records, tile_counts);
+  hipLaunchKernelGGL(bin_count_kernel, dim3(bin_blocks(n_records)), dim3(256), 0, st, records,
+                     views, n_views, n_records, tile_counts, hit_mask, big_list, big_count);
+  hipLaunchKernelGGL(bin_big_kernel<false>, dim3(kBigBlocks), dim3(256), 0, st, records, views,
+                     n_views, big_list, big_count, tile_counts, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -345,11 +481,14 @@ hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint
 }
 
 hipError_t launch_bin_emit(const float* records, const DevView* views, int n_views,
-                           uint32_t n_records, uint32_t* tile_cursor, const DevStatus* status,
-                           unsigned long long* comp, hipStream_t st) {
+                           uint32_t n_records, const uint32_t* hit_mask, const uint32_t* big_list,
+                           const uint32_t* big_count, uint32_t* tile_cursor,
+                           const DevStatus* status, unsigned long long* comp, hipStream_t st) {
   if (n_records == 0) return hipSuccess;
-  hipLaunchKernelGGL(bin_emit_kernel, dim3((n_records + 255) / 256), dim3(256), 0, st, records,
-                     views, n_views, n_records, tile_cursor, status, comp);
+  hipLaunchKernelGGL(bin_emit_kernel, dim3(bin_blocks(n_records)), dim3(256), 0, st, records,
+                     views, n_views, n_records, hit_mask, tile_cursor, status, comp);
+  hipLaunchKernelGGL(bin_big_kernel<true>, dim3(kBigBlocks), dim3(256), 0, st, records, views,
+                     n_views, big_list, big_count, nullptr, tile_cursor, status, comp);
   return hipGetLastError();
 }
 

@@ -120,7 +120,12 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int sce
   for (int k = 0; k < pr.F; ++k) compact[int64_t(k) * S.n + t] = out[k];
 }
 
-// dparams[:, i] = compact[:, offs[i]] for live primitives, 0 otherwise.
+// dparams[k, i] = compact[k, offs[i]] for live primitives, 0 otherwise.  One
+// primitive per thread; the rows go in chunks whose loads are all issued
+// before their stores, so a wavefront waits for memory once per chunk
+// rather than once per row.
+constexpr int kScatterChunk = 9;
+
 __global__ void __launch_bounds__(256) scatter_dparams_kernel(DevScene S,
                                                               const uint32_t* __restrict__ live,
                                                               const uint32_t* __restrict__ offs,
@@ -129,8 +134,19 @@ __global__ void __launch_bounds__(256) scatter_dparams_kernel(DevScene S,
   if (i >= S.n) return;
   const bool is_live = live[i] != 0;
   const int64_t j = is_live ? int64_t(offs[i]) : 0;
-  for (int k = 0; k < S.F; ++k)
-    S.dparams[int64_t(k) * S.n + i] = is_live ? compact[int64_t(k) * S.n + j] : 0.0f;
+  for (int k0 = 0; k0 < S.F; k0 += kScatterChunk) {
+    float v[kScatterChunk];
+#pragma unroll
+    for (int q = 0; q < kScatterChunk; ++q) {
+      const int k = k0 + q;
+      v[q] = (is_live && k < S.F) ? compact[int64_t(k) * S.n + j] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < kScatterChunk; ++q) {
+      const int k = k0 + q;
+      if (k < S.F) S.dparams[int64_t(k) * S.n + i] = v[q];
+    }
+  }
 }
 
 template <typename T, int C, int ROT>
@@ -150,7 +166,8 @@ static hipError_t pre_bwd_t(const DevScene& S, int scene, const DevView* views, 
   const unsigned blocks = unsigned((S.n + 255) / 256);
   hipLaunchKernelGGL((preprocess_bwd_kernel<T, C, ROT>), dim3(blocks), dim3(256), 0, st, S, scene,
                      views, n_views, records, grad2d, list, n_live, compact);
-  hipLaunchKernelGGL(scatter_dparams_kernel, dim3(blocks), dim3(256), 0, st, S, live, offs, compact);
+  hipLaunchKernelGGL(scatter_dparams_kernel, dim3(blocks), dim3(256), 0, st, S, live, offs,
+                     compact);
   return hipGetLastError();
 }
 

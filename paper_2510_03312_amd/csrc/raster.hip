@@ -202,6 +202,26 @@ __device__ __forceinline__ void row_scan_all(float* v) {
 #pragma unroll
   for (int q = 0; q < N; ++q) v[q] += dpp_shr<0x118>(v[q]);
 }
+// Lane exchanges of gfx950: swap_halves(a, b) returns (a with its upper 32
+// lanes replaced by b's lower 32, b with its lower 32 replaced by a's upper
+// 32); swap_rows(a, b) does the same between a's odd rows and b's even rows
+// (rows of 16 lanes).
+struct FPair {
+  float a, b;
+};
+__device__ __forceinline__ FPair swap_halves(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return FPair{__uint_as_float(r[0]), __uint_as_float(r[1])};
+}
+__device__ __forceinline__ FPair swap_rows(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return FPair{__uint_as_float(r[0]), __uint_as_float(r[1])};
+}
+__device__ __forceinline__ float opaque_zero() {
+  float z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return z;
+}
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
@@ -212,7 +232,7 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 
 template <int TW, int TH, int BATCH>
 __device__ __forceinline__ void raster_bwd_tile(
-    uint32_t tile, float4* s0, float4* s1, float4* s2, float* s_rows,
+    uint32_t tile, float4* s0, float4* s1, float4* s2,
     const float* __restrict__ records,
     const uint32_t* __restrict__ values, const uint32_t* __restrict__ ranges,
     const DevView* __restrict__ views, int n_views, const float* __restrict__ t_ws,
@@ -282,8 +302,10 @@ __device__ __forceinline__ void raster_bwd_tile(
       const ColTerms ct = col_terms(g0, dx);
       const float inv_o = hw_exp2(-g1.z);   // 1 / o: d sigma / d o = sigma / o
       // per-lane sums over the lane's pixels
-      float a_r = 0.f, a_g = 0.f, a_b = 0.f, a_o = 0.f, a_be = 0.f;
-      float a_dr = 0.f, a_dry = 0.f, a_dryy = 0.f;
+      // (zeros the compiler cannot rematerialise: otherwise it re-creates
+      // them on every path that skips the first pixel's update)
+      float a_r = opaque_zero(), a_g = opaque_zero(), a_b = opaque_zero(), a_o = opaque_zero();
+      float a_be = opaque_zero(), a_dr = opaque_zero(), a_dry = opaque_zero(), a_dryy = opaque_zero();
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
@@ -332,27 +354,34 @@ __device__ __forceinline__ void raster_bwd_tile(
       gv[8] = a_g;
       gv[9] = a_b;
       gv[5] = a_o * inv_o;
-      // sums over the wavefront: row scans, the four row totals through LDS,
-      // lane q < 10 adds the four totals of field q and issues its atomic
-      // (the ten scans are independent: one DPP step of every field before
-      // the next step, so no step waits on the previous one's result)
-      row_scan_all<kGradFloats>(gv);
-      if ((lane & 15) == 15) {
+      // sums over the wavefront: halves folded onto each other (permlane32
+      // swap: field 2p in lanes 0-31, 2p+1 in lanes 32-63), row pairs folded
+      // (permlane16 swap: one field per row), DPP scans within the rows;
+      // lane 15 of each row ends with the totals of its rows' fields
+      float h[5];
 #pragma unroll
-        for (int q = 0; q < kGradFloats; ++q) s_rows[(lane >> 4) * kGradFloats + q] = gv[q];
+      for (int p = 0; p < 5; ++p) {
+        const FPair sw = swap_halves(gv[2 * p], gv[2 * p + 1]);
+        h[p] = sw.a + sw.b;
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_s_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      if (lane < kGradFloats) {
-        const float tot = (s_rows[lane] + s_rows[kGradFloats + lane]) +
-                          (s_rows[2 * kGradFloats + lane] + s_rows[3 * kGradFloats + lane]);
-        if (tot != 0.0f) {
-          const uint32_t rec = __float_as_uint(g2.w);
-          atomicAdd(grad2d + size_t(rec) * kGradFloats + lane, tot);
-        }
+      float t3[3];
+      {
+        const FPair s0 = swap_rows(h[0], h[1]);   // rows: fields 0, 2, 1, 3
+        const FPair s1 = swap_rows(h[2], h[3]);   // rows: fields 4, 6, 5, 7
+        const FPair s2 = swap_rows(h[4], h[4]);   // rows: fields 8, 8, 9, 9
+        t3[0] = s0.a + s0.b;
+        t3[1] = s1.a + s1.b;
+        t3[2] = s2.a + s2.b;
       }
-      __builtin_amdgcn_s_barrier();
+      row_scan_all<3>(t3);
+      if ((lane & 15) == 15) {
+        const int row = lane >> 4;
+        const int sub = row == 1 ? 2 : (row == 2 ? 1 : row);
+        float* g = grad2d + size_t(__float_as_uint(g2.w)) * kGradFloats;
+        if (t3[0] != 0.0f) atomicAdd(g + sub, t3[0]);
+        if (t3[1] != 0.0f) atomicAdd(g + 4 + sub, t3[1]);
+        if ((row & 1) == 0 && t3[2] != 0.0f) atomicAdd(g + 8 + (row >> 1), t3[2]);
+      }
     }
     hi = lo;
   }
@@ -367,9 +396,8 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(
     const float* __restrict__ d_tfinal, const float* __restrict__ l1_image,
     const float* __restrict__ l1_target, float l1_scale, float* __restrict__ grad2d) {
   __shared__ float4 s0[BATCH], s1[BATCH], s2[BATCH];
-  __shared__ float s_rows[4 * kGradFloats];
   for (uint32_t tile = next_tile(work, true); tile < n_tiles; tile = next_tile(work, false))
-    raster_bwd_tile<TW, TH, BATCH>(tile, s0, s1, s2, s_rows, records, values, ranges, views, n_views, t_ws,
+    raster_bwd_tile<TW, TH, BATCH>(tile, s0, s1, s2, records, values, ranges, views, n_views, t_ws,
                                    ncontrib, d_image, d_tfinal, l1_image, l1_target, l1_scale,
                                    grad2d);
 }

@@ -19,7 +19,8 @@
 //                     ping-ponging with the segment's slice of the output
 //                     key buffer; digits that are constant over the segment
 //                     are skipped.
-// It also writes the tile's [start, end) range (empty after an overflow).
+// It also writes the tile's [start, end) range ((0, 0) for an empty tile and
+// for every tile after an overflow).
 #include "ubs_internal.hpp"
 
 namespace ubs {
@@ -128,8 +129,8 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_sort_kernel(
   const bool overflow = status->overflow != 0u;
   for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const uint32_t n = overflow ? 0u : tile_counts[t];
-    const uint32_t end = overflow ? 0u : tile_end[t];
-    const uint32_t start = end - n;
+    const uint32_t end = n ? tile_end[t] : 0u;
+    const uint32_t start = end - n;   // an empty tile's range is (0, 0)
     if (threadIdx.x == 0) {
       ranges[2 * size_t(t)] = start;
       ranges[2 * size_t(t) + 1] = end;

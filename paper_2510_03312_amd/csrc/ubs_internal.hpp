@@ -84,6 +84,8 @@ struct Layout {
   ubs_layout pub;
   uint64_t off_views, off_scenes, off_offsets, off_blocksums;
   uint64_t off_tile_counts, off_tile_cursor;  // pairs per tile; segment cursors
+  uint64_t off_hit_mask;             // per record: hits among its candidate tiles
+  uint64_t off_big_list;             // records binned by a workgroup each
   uint64_t off_comp;                 // emitted (depth bits << 32 | record) per tile segment
   uint64_t off_keys0, off_values0;   // sorted keys and values
   uint64_t off_tfinal_ws;            // final transmittance kept for the adjoint

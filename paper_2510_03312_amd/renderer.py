@@ -271,7 +271,7 @@ class GraphFrame:
 
     def __init__(self, renderer: Renderer, scenes: Sequence[SceneRef], views: Sequence, *,
                  l1_target: Optional[torch.Tensor] = None, d_image: Optional[torch.Tensor] = None,
-                 backward: bool = True, headroom: float = 1.25, stage_events=None):
+                 backward: bool = True, headroom: float = 1.25):
         if backward and (l1_target is None) == (d_image is None):
             raise ValueError("give exactly one of l1_target or d_image")
         self.r = renderer
@@ -292,18 +292,15 @@ class GraphFrame:
         self.backward = backward
         self._step()                       # eager warm-up of the exact sequence
         torch.cuda.synchronize()
-        self.graph = self.capture(stage_events)
+        self.graph = self.capture()
 
-    def capture(self, stage_events=None) -> "torch.cuda.CUDAGraph":
-        """Captures the frame once more into a new graph; with ``stage_events``
-        (a ``StageTimer`` slot) the graph also records the per-stage events."""
+    def capture(self) -> "torch.cuda.CUDAGraph":
+        """Captures the frame once more into a new graph (per-stage timing is
+        taken from plain calls, ``step()`` with a ``StageTimer`` attached)."""
         g = torch.cuda.CUDAGraph()
-        self.frame.c.stage_events = stage_events
-        try:
-            with torch.cuda.graph(g):
-                self._step()
-        finally:
-            self.frame.c.stage_events = None
+        self.frame.c.stage_events = None
+        with torch.cuda.graph(g):
+            self._step()
         torch.cuda.synchronize()
         return g
 

@@ -28,6 +28,8 @@ def hip() -> ctypes.CDLL:
         h.hipEventElapsedTime.restype = ctypes.c_int
         h.hipEventQuery.argtypes = [ctypes.c_void_p]
         h.hipEventQuery.restype = ctypes.c_int
+        h.hipGetLastError.argtypes = []
+        h.hipGetLastError.restype = ctypes.c_int
         _hip = h
     return _hip
 
@@ -61,16 +63,22 @@ class StageTimer:
         frame_c.stage_events = None
 
     def elapsed_ms(self, slot: int) -> Dict[str, float]:
-        """Stage durations of one slot (only stages that ran)."""
+        """Stage durations of one slot (only stages that ran: the events of a
+        stage that did not run were never recorded, and asking for their
+        elapsed time fails; that error is cleared so that it does not
+        surface at the next HIP call)."""
         out = {}
         arr = self.arrays[slot]
         for s, name in enumerate(_lib.STAGES):
             a, b = arr[2 * s], arr[2 * s + 1]
             if hip().hipEventQuery(a) != 0 or hip().hipEventQuery(b) != 0:
+                hip().hipGetLastError()
                 continue
             ms = ctypes.c_float()
             if hip().hipEventElapsedTime(ctypes.byref(ms), a, b) == 0:
                 out[name] = float(ms.value)
+            else:
+                hip().hipGetLastError()
         return out
 
     def close(self) -> None:

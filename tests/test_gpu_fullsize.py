@@ -111,6 +111,7 @@ def test_full_size_sort_invariants(full):
     assert np.array_equal((ranges[:, 1] - ranges[:, 0]).astype(np.int64), counts)
     nz = counts > 0
     assert np.all(tiles[ranges[nz, 0]] == np.flatnonzero(nz))
+    assert np.all(ranges[~nz] == 0)
     # depth word = float32 bits of the record's depth; equal keys in record order
     depth_bits = (keys & np.uint64(0xffffffff)).astype(np.uint32)
     assert np.array_equal(depth_bits, rec[vals, 11].astype(np.float32).view(np.uint32))
