@@ -10,8 +10,10 @@
 namespace ubs {
 
 hipError_t launch_preprocess_fwd(bool fp64, const DevScene& S, int scene, const DevView* views,
-                                 int n_views, float* records, uint32_t* live, DevStatus* status,
-                                 hipStream_t st);
+                                 int n_views, float* records, uint32_t* live, uint32_t* partial,
+                                 uint32_t stride, hipStream_t st);
+hipError_t launch_sum_partials(const uint32_t* partial, uint32_t n, uint32_t stride,
+                               DevStatus* status, hipStream_t st);
 hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const DevView* views,
                                  int n_views, const float* records, const float* grad2d,
                                  const uint32_t* live, const uint32_t* offs, const uint32_t* list,
@@ -213,6 +215,9 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.off_live_list = take(4 * n_prims);
   l.off_live_count = take(8 * uint64_t(f->n_scenes > 0 ? f->n_scenes : 1));
   l.off_grad_compact = take(4 * n_grad_compact);
+  // per-workgroup counts of the preprocess launches (one launch per scene)
+  l.n_pre_partials = int64_t(n_prims / 256 + uint64_t(f->n_scenes) + 1);
+  l.off_pre_partials = take(8 * uint64_t(l.n_pre_partials));
   l.pub.bytes = off;
   l.pub.off_keys = l.off_keys0;
   l.pub.off_values = l.off_values0;
@@ -287,13 +292,19 @@ ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes, u
   const bool fp64 = (frame->tuning.flags & UBS_TUNE_PRE_FP32) == 0;
   float* records = at<float>(ws, L.pub.off_records);
   stage_mark(frame, UBS_STAGE_PREPROCESS, 0, s);
+  uint32_t* partial = at<uint32_t>(ws, L.off_pre_partials);
+  const uint32_t stride = uint32_t(L.n_pre_partials);
+  uint32_t block_base = 0;
   for (int sc = 0; sc < frame->n_scenes; ++sc) {
     bool used = false;
     for (const DevView& v : p.dv) used = used || v.scene == sc;
-    if (!used) continue;
+    if (!used || p.ds[sc].n == 0) continue;
     UBS_HIP(launch_preprocess_fwd(fp64, p.ds[sc], sc, views, frame->n_views, records,
-                                  at<uint32_t>(ws, L.off_live) + p.ds[sc].prim_base, status, s));
+                                  at<uint32_t>(ws, L.off_live) + p.ds[sc].prim_base,
+                                  partial + block_base, stride, s));
+    block_base += uint32_t((p.ds[sc].n + 255) / 256);
   }
+  UBS_HIP(launch_sum_partials(partial, block_base, stride, status, s));
   stage_mark(frame, UBS_STAGE_PREPROCESS, 1, s);
   return UBS_OK;
 }

@@ -13,7 +13,8 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
                                                              const DevView* __restrict__ views,
                                                              int n_views, float* __restrict__ records,
                                                              uint32_t* __restrict__ live,
-                                                             DevStatus* __restrict__ status) {
+                                                             uint32_t* __restrict__ partial,
+                                                             uint32_t partial_stride) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   const bool active = i < S.n;
   bool finite = true;
@@ -57,8 +58,8 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
     rp[2] = o2;
   }
   if (active) live[i] = visible > 0 ? 1u : 0u;
-  // workgroup-aggregated counters: one atomic per workgroup and counter (the
-  // status words are single addresses every workgroup updates)
+  // per-workgroup counts (no atomics on a shared word: those serialise across
+  // the chip); sum_partials_kernel adds them into the status block
   __shared__ uint32_t s_cnt[2];
   if (threadIdx.x == 0) { s_cnt[0] = 0; s_cnt[1] = 0; }
   __syncthreads();
@@ -73,9 +74,41 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (s_cnt[0]) atomicAdd(&status->n_nonfinite, s_cnt[0]);
-    if (s_cnt[1]) atomicAdd(&status->n_visible, s_cnt[1]);
+    partial[blockIdx.x] = s_cnt[1];
+    partial[partial_stride + blockIdx.x] = s_cnt[0];
   }
+}
+
+// status->n_visible / n_nonfinite = sums of the n per-workgroup counts.
+__global__ void __launch_bounds__(256) sum_partials_kernel(const uint32_t* __restrict__ partial,
+                                                           uint32_t n, uint32_t stride,
+                                                           DevStatus* __restrict__ status) {
+  __shared__ uint32_t s_sum[2][4];
+  uint32_t vis = 0, nf = 0;
+  for (uint32_t k = threadIdx.x; k < n; k += 256) {
+    vis += partial[k];
+    nf += partial[stride + k];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    vis += __shfl_xor(vis, o, 64);
+    nf += __shfl_xor(nf, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_sum[0][threadIdx.x >> 6] = vis;
+    s_sum[1][threadIdx.x >> 6] = nf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    status->n_visible = s_sum[0][0] + s_sum[0][1] + s_sum[0][2] + s_sum[0][3];
+    status->n_nonfinite = s_sum[1][0] + s_sum[1][1] + s_sum[1][2] + s_sum[1][3];
+  }
+}
+
+hipError_t launch_sum_partials(const uint32_t* partial, uint32_t n, uint32_t stride,
+                               DevStatus* status, hipStream_t st) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, partial, n, stride, status);
+  return hipGetLastError();
 }
 
 // Thread t runs the adjoint of the t-th live primitive of the compacted list
@@ -151,10 +184,11 @@ __global__ void __launch_bounds__(256) scatter_dparams_kernel(DevScene S,
 
 template <typename T, int C, int ROT>
 static hipError_t pre_fwd_t(const DevScene& S, int scene, const DevView* views, int n_views,
-                            float* records, uint32_t* live, DevStatus* status, hipStream_t st) {
+                            float* records, uint32_t* live, uint32_t* partial, uint32_t stride,
+                            hipStream_t st) {
   const unsigned blocks = unsigned((S.n + 255) / 256);
   hipLaunchKernelGGL((preprocess_fwd_kernel<T, C, ROT>), dim3(blocks), dim3(256), 0, st, S, scene,
-                     views, n_views, records, live, status);
+                     views, n_views, records, live, partial, stride);
   return hipGetLastError();
 }
 
@@ -173,16 +207,17 @@ static hipError_t pre_bwd_t(const DevScene& S, int scene, const DevView* views, 
 
 template <typename T>
 static hipError_t pre_fwd_dispatch(const DevScene& S, int scene, const DevView* views, int n_views,
-                                   float* records, uint32_t* live, DevStatus* status, hipStream_t st) {
+                                   float* records, uint32_t* live, uint32_t* partial,
+                                   uint32_t stride, hipStream_t st) {
   const int C = S.dim - 3;
   if (S.rot == UBS_ROT_QUAT) {
-    if (C == 0) return pre_fwd_t<T, 0, 0>(S, scene, views, n_views, records, live, status, st);
-    if (C == 3) return pre_fwd_t<T, 3, 0>(S, scene, views, n_views, records, live, status, st);
-    if (C == 4) return pre_fwd_t<T, 4, 0>(S, scene, views, n_views, records, live, status, st);
+    if (C == 0) return pre_fwd_t<T, 0, 0>(S, scene, views, n_views, records, live, partial, stride, st);
+    if (C == 3) return pre_fwd_t<T, 3, 0>(S, scene, views, n_views, records, live, partial, stride, st);
+    if (C == 4) return pre_fwd_t<T, 4, 0>(S, scene, views, n_views, records, live, partial, stride, st);
   } else {
-    if (C == 0) return pre_fwd_t<T, 0, 1>(S, scene, views, n_views, records, live, status, st);
-    if (C == 3) return pre_fwd_t<T, 3, 1>(S, scene, views, n_views, records, live, status, st);
-    if (C == 4) return pre_fwd_t<T, 4, 1>(S, scene, views, n_views, records, live, status, st);
+    if (C == 0) return pre_fwd_t<T, 0, 1>(S, scene, views, n_views, records, live, partial, stride, st);
+    if (C == 3) return pre_fwd_t<T, 3, 1>(S, scene, views, n_views, records, live, partial, stride, st);
+    if (C == 4) return pre_fwd_t<T, 4, 1>(S, scene, views, n_views, records, live, partial, stride, st);
   }
   return hipErrorInvalidValue;
 }
@@ -206,12 +241,14 @@ static hipError_t pre_bwd_dispatch(const DevScene& S, int scene, const DevView* 
   return hipErrorInvalidValue;
 }
 
+// partial: this launch's slice of the per-workgroup counts (visible records
+// at partial[b], non-finite primitives at partial[stride + b]).
 hipError_t launch_preprocess_fwd(bool fp64, const DevScene& S, int scene, const DevView* views,
-                                 int n_views, float* records, uint32_t* live, DevStatus* status,
-                                 hipStream_t st) {
+                                 int n_views, float* records, uint32_t* live, uint32_t* partial,
+                                 uint32_t stride, hipStream_t st) {
   if (S.n == 0) return hipSuccess;
-  return fp64 ? pre_fwd_dispatch<double>(S, scene, views, n_views, records, live, status, st)
-              : pre_fwd_dispatch<float>(S, scene, views, n_views, records, live, status, st);
+  return fp64 ? pre_fwd_dispatch<double>(S, scene, views, n_views, records, live, partial, stride, st)
+              : pre_fwd_dispatch<float>(S, scene, views, n_views, records, live, partial, stride, st);
 }
 
 hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const DevView* views,

@@ -91,6 +91,8 @@ struct Layout {
   uint64_t off_tfinal_ws;            // final transmittance kept for the adjoint
   uint64_t off_live, off_live_list, off_live_count;  // per-primitive live flags, compacted list, counts
   uint64_t off_grad_compact;         // adjoint output of live primitives, [F][n] per scene
+  uint64_t off_pre_partials;         // per-workgroup preprocess counts [2][n_pre_partials]
+  int64_t n_pre_partials;
   int64_t n_prims;                   // sum over scenes of primitives
   int64_t n_scan_blocks;
   int32_t rec_bits, digit_bits;
