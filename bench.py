@@ -62,6 +62,8 @@ WORKLOADS = {
                      "t = k/7) in one batched frame, forward+backward, L1 loss"),
     "cfg4": ("cfg4", "4 scenes of 7-D Beta primitives (100k/500k/1.5M/3M), 32 views of uneven "
                      "resolution in one batched frame, autotuned, forward+backward, L1 loss"),
+    "adam": ("headline", "optimiser step (regularisers, Adam, spatial noise) over the parameters "
+                         "of 1,000,000 7-D primitives (45 rows)"),
 }
 
 
@@ -391,6 +393,46 @@ def run_batched(args, name, desc):
     }
 
 
+def run_adam(args, name, desc):
+    """The optimiser step alone: one streaming pass over params, dparams, m,
+    v (and three noise rows), writing params, m, v."""
+    import torch
+    from paper_2510_03312_amd.optim import adam_step
+    from synth import make_config
+
+    cfg = make_config(name)
+    sc = cfg["scenes"][0]
+    dev = torch.device("cuda:0")
+    F, n = sc.params.shape
+    params = torch.from_numpy(sc.params).to(dev)
+    g = torch.randn(F, n, device=dev) * 1e-3
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    noise = torch.randn(3, n, device=dev)
+    for t in range(1, args.warmup + 1):
+        adam_step(params, g, m, v, t, sc.dim, sc.rot, noise=noise)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for t in range(args.warmup + 1, args.warmup + 1 + args.steps):
+        adam_step(params, g, m, v, t, sc.dim, sc.rot, noise=noise)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    nbytes = 4.0 * F * n * 7 + 4.0 * 3 * n   # read p, g, m, v; write p, m, v; read noise
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {
+        "metric": "optimiser steps/s (Adam + regularisers + noise, 1M 7-D prims)",
+        "value": round(1000.0 / ms, 2), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": desc, "primitives": n, "rows": F},
+        "roofline": {"bound": "hbm", "kernel": "adam", "achieved": round(gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_step": nbytes},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -414,7 +456,12 @@ def main() -> int:
     torch.cuda.set_device(0)
     name, desc = WORKLOADS[args.workload]
     log(f"[bench] workload {args.workload}")
-    res = run_batched(args, name, desc) if name in ("cfg3", "cfg4") else run_single(args, name, desc)
+    if args.workload == "adam":
+        res = run_adam(args, name, desc)
+    elif name in ("cfg3", "cfg4"):
+        res = run_batched(args, name, desc)
+    else:
+        res = run_single(args, name, desc)
     print(json.dumps(res), flush=True)
     return 0
 

@@ -284,6 +284,46 @@ ubs_status ubs_render_bwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
                           const float* d_image, const float* d_t_final,
                           const float* l1_image, const float* l1_target, void* stream);
 
+/*
+ * Optimiser step settings (Sec. 4.5 and Sec. 5.1).  Defaults in the paper:
+ * lr_mu_x 1.6e-4, lr_opacity 5e-2, lr_scale 5e-3 (the three log_s_x rows),
+ * lr_other 1e-3 (every other row); lambda_o 0.01, lambda_s 0.01 (the
+ * paper's lambda_Sigma), lambda_eps 1.  beta1, beta2, eps: Adam's (the paper
+ * gives none; 0.9, 0.999, 1e-15 are the conventional choice).  step: the
+ * 1-based Adam step t (bias corrections 1 - beta^t).
+ */
+typedef struct {
+  float lr_mu_x, lr_opacity, lr_scale, lr_other;
+  float beta1, beta2, eps;
+  float lambda_o, lambda_s, lambda_eps;
+  int32_t step;
+  int32_t _pad;
+} ubs_adam;
+
+/*
+ * ubs_adam_step -- one optimisation step of a scene's parameters, in place.
+ * Paper: Section 4.5 (loss with lambda_o sum |o_i| + lambda_Sigma sum
+ * ||s_i||_1; spatial noise injection mu_x += lambda_eps epsilon) and
+ * Section 5.1 (Adam, learning rate per parameter group).
+ * params, m, v: device float32 [F][n] (ubs_scene layout), read and written;
+ * m and v are Adam's moment estimates, zero before step 1, owned by the
+ * caller.  dparams: device float32 [F][n], d loss / d params of the
+ * reconstruction terms (ubs_render_bwd's output); the regulariser gradients
+ * lambda_o sign(o) (opacity row) and lambda_s exp(log s) (log_s_x rows) are
+ * added in-kernel.  noise: device float32 [3][n] epsilon for the spatial
+ * means (added after the Adam update, times lambda_eps), or NULL for none.
+ * Per element: g = dparams + regulariser; m = beta1 m + (1 - beta1) g;
+ * v = beta2 v + (1 - beta2) g^2; p -= lr m / (1 - beta1^t) /
+ * (sqrt(v / (1 - beta2^t)) + eps).  Nothing is clamped.  Asynchronous on
+ * stream; no buffer may alias another.  Errors: UBS_ERR_ARG for a NULL cfg
+ * or buffer (n > 0), dim/rot outside the ubs_scene range, n < 0, step < 1,
+ * beta outside [0, 1) or eps < 0; UBS_ERR_UNSUPPORTED for dim 4/5;
+ * UBS_ERR_HIP if the launch fails.
+ */
+ubs_status ubs_adam_step(const ubs_adam* cfg, int32_t dim, int32_t rot, int64_t n,
+                         float* params, const float* dparams, float* m, float* v,
+                         const float* noise, void* stream);
+
 /* Number of parameter rows F for a scene (0 for an unsupported dim/rot). */
 int32_t ubs_param_count(int32_t dim, int32_t rot);
 

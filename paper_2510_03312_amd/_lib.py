@@ -27,7 +27,7 @@ UBS_TUNE_PERSISTENT = 1
 UBS_TUNE_PRE_FP32 = 2
 
 EXPORTS = ("ubs_preprocess", "ubs_bin_sort", "ubs_render_fwd", "ubs_render_bwd",
-           "ubs_param_count", "ubs_abi_version")
+           "ubs_adam_step", "ubs_param_count", "ubs_abi_version")
 
 
 class UbsScene(ctypes.Structure):
@@ -71,6 +71,13 @@ class UbsStatusBlock(ctypes.Structure):
                 ("n_visible", c_uint32), ("sort_stalled", c_uint32), ("_pad", c_uint32 * 10)]
 
 
+class UbsAdam(ctypes.Structure):
+    _fields_ = [("lr_mu_x", c_float), ("lr_opacity", c_float), ("lr_scale", c_float),
+                ("lr_other", c_float), ("beta1", c_float), ("beta2", c_float), ("eps", c_float),
+                ("lambda_o", c_float), ("lambda_s", c_float), ("lambda_eps", c_float),
+                ("step", c_int32), ("_pad", c_int32)]
+
+
 class UbsError(RuntimeError):
     def __init__(self, fn: str, code: int):
         super().__init__(f"{fn} returned {STATUS_NAMES.get(code, code)}")
@@ -96,6 +103,9 @@ def load() -> ctypes.CDLL:
                                      c_void_p, c_void_p]
         for fn in ("ubs_preprocess", "ubs_bin_sort", "ubs_render_fwd", "ubs_render_bwd"):
             getattr(L, fn).restype = c_int32
+        L.ubs_adam_step.argtypes = [POINTER(UbsAdam), c_int32, c_int32, c_int64, c_void_p,
+                                    c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.ubs_adam_step.restype = c_int32
         L.ubs_param_count.argtypes = [c_int32, c_int32]
         L.ubs_param_count.restype = c_int32
         L.ubs_abi_version.argtypes = []
@@ -135,6 +145,13 @@ def ubs_render_bwd(frame: UbsFrame, ws: int, ws_bytes: int, d_image: int, d_t_fi
                                  d_t_final or None, l1_image or None, l1_target or None,
                                  stream or None)
     return _check("ubs_render_bwd", code) if check else code
+
+
+def ubs_adam_step(cfg: UbsAdam, dim: int, rot: int, n: int, params: int, dparams: int, m: int,
+                  v: int, noise: int, stream: int, check: bool = True) -> int:
+    code = load().ubs_adam_step(ctypes.byref(cfg), dim, rot, n, params, dparams, m, v, noise,
+                                stream)
+    return _check("ubs_adam_step", code) if check else code
 
 
 def ubs_param_count(dim: int, rot: int) -> int:

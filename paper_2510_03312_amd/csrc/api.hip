@@ -12,8 +12,9 @@ namespace ubs {
 hipError_t launch_preprocess_fwd(bool fp64, const DevScene& S, int scene, const DevView* views,
                                  int n_views, float* records, uint32_t* live, uint32_t* partial,
                                  uint32_t stride, hipStream_t st);
-hipError_t launch_sum_partials(const uint32_t* partial, uint32_t n, uint32_t stride,
-                               DevStatus* status, hipStream_t st);
+hipError_t launch_bin_prepare(uint32_t* words, size_t n_words, const uint32_t* partial,
+                              uint32_t n_partials, uint32_t stride, DevStatus* status,
+                              hipStream_t st);
 hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const DevView* views,
                                  int n_views, const float* records, const float* grad2d,
                                  const uint32_t* live, const uint32_t* offs, const uint32_t* list,
@@ -56,13 +57,13 @@ struct ViewChunk {
   int32_t first, count;
 };
 
-__global__ void upload_views_kernel(ViewChunk c, DevView* __restrict__ dst) {
+// Writes a chunk of view descriptors; the first chunk's launch also clears
+// the status block (s != nullptr).
+__global__ void upload_views_kernel(ViewChunk c, DevView* __restrict__ dst,
+                                    DevStatus* __restrict__ s) {
   const int k = threadIdx.x;
   if (k < c.count) dst[c.first + k] = c.v[k];
-}
-
-__global__ void reset_status_kernel(DevStatus* __restrict__ s) {
-  if (threadIdx.x == 0) {
+  if (s && k == 0) {
     s->pairs_needed = 0;
     s->overflow = 0;
     s->n_nonfinite = 0;
@@ -240,6 +241,21 @@ struct Plan {
   std::vector<DevScene> ds;
 };
 
+// Scenes some view renders (preprocess launches one kernel for each).
+static bool scene_used(const Plan& p, int sc) {
+  for (const DevView& v : p.dv)
+    if (v.scene == sc) return true;
+  return false;
+}
+
+// Workgroups of the preprocess launches: the per-workgroup counts they left.
+static uint32_t pre_partials_used(const Plan& p) {
+  uint32_t n = 0;
+  for (int sc = 0; sc < int(p.ds.size()); ++sc)
+    if (scene_used(p, sc) && p.ds[sc].n > 0) n += uint32_t((p.ds[sc].n + 255) / 256);
+  return n;
+}
+
 static ubs_status prepare(const ubs_frame* f, void* ws, uint64_t ws_bytes, Plan* p) {
   const ubs_status st = plan(f, &p->L, &p->dv, &p->ds);
   if (st != UBS_OK) return st;
@@ -280,13 +296,13 @@ ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes, u
   const Layout& L = p.L;
   DevStatus* status = at<DevStatus>(ws, L.pub.off_status);
   DevView* views = at<DevView>(ws, L.off_views);
-  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, status);
-  for (int first = 0; first < frame->n_views; first += kViewChunk) {
+  for (int first = 0; first == 0 || first < frame->n_views; first += kViewChunk) {
     ViewChunk c{};
     c.first = first;
     c.count = frame->n_views - first < kViewChunk ? frame->n_views - first : kViewChunk;
     for (int k = 0; k < c.count; ++k) c.v[k] = p.dv[first + k];
-    hipLaunchKernelGGL(upload_views_kernel, dim3(1), dim3(64), 0, s, c, views);
+    hipLaunchKernelGGL(upload_views_kernel, dim3(1), dim3(64), 0, s, c, views,
+                       first == 0 ? status : nullptr);
   }
   UBS_HIP(hipGetLastError());
   const bool fp64 = (frame->tuning.flags & UBS_TUNE_PRE_FP32) == 0;
@@ -304,7 +320,6 @@ ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes, u
                                   partial + block_base, stride, s));
     block_base += uint32_t((p.ds[sc].n + 255) / 256);
   }
-  UBS_HIP(launch_sum_partials(partial, block_base, stride, status, s));
   stage_mark(frame, UBS_STAGE_PREPROCESS, 1, s);
   return UBS_OK;
 }
@@ -329,7 +344,9 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
   // the word after the tile counts counts the records binned by workgroups
   uint32_t* big_count = tile_counts + n_tiles;
   uint32_t* big_list = at<uint32_t>(ws, L.off_big_list);
-  UBS_HIP(launch_fill_u32(tile_counts, size_t(n_tiles) + 1, 0u, s));
+  // clear the counters; also add up preprocess's per-workgroup counts
+  UBS_HIP(launch_bin_prepare(tile_counts, size_t(n_tiles) + 1, at<uint32_t>(ws, L.off_pre_partials),
+                             pre_partials_used(p), uint32_t(L.n_pre_partials), status, s));
   uint32_t* hit_mask = at<uint32_t>(ws, L.off_hit_mask);
   UBS_HIP(launch_bin_count(records, views, frame->n_views, n_rec, tile_counts, hit_mask, big_list,
                            big_count, s));

@@ -381,17 +381,31 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_u32(uint32_t v, uint32_
   return wbase + x - v;
 }
 
+// Sum over the 256 threads of a workgroup in 64 bits (a count total must not
+// wrap: it decides the overflow flag).
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v,
+                                                            unsigned long long* lds4) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) lds4[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const unsigned long long t = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+  __syncthreads();
+  return t;
+}
+
+// Per-block totals, saturated at 2^32 - 1 (a saturated total makes the
+// grand total exceed any capacity, so the overflow flag is still raised).
 __global__ void __launch_bounds__(kScanThreads) scan_tile_sums_kernel(
     const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ tile_sums) {
-  __shared__ uint32_t lds[8];
+  __shared__ unsigned long long lds4[4];
   const size_t base = size_t(blockIdx.x) * kScanTile + size_t(threadIdx.x) * kScanItems;
-  uint32_t s = 0;
+  unsigned long long s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k)
     if (base + k < n) s += in[base + k];
-  uint32_t tot;
-  block_exclusive_scan_u32(s, lds, &tot);
-  if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+  const unsigned long long tot = block_sum_u64(s, lds4);
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot > 0xffffffffull ? 0xffffffffu : uint32_t(tot);
 }
 
 // One block scans all tile sums in place (exclusive) and writes the total
@@ -465,9 +479,55 @@ hipError_t launch_bin_count(const float* records, const DevView* views, int n_vi
   return hipGetLastError();
 }
 
+// Exclusive scan of up to kSingleScanMax values by one workgroup, chunk by
+// chunk with a running carry (one launch instead of three); same outputs as
+// the three-kernel scan.
+constexpr uint32_t kSingleScanMax = 16u * kScanTile;
+
+__global__ void __launch_bounds__(kScanThreads) scan_single_kernel(
+    const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ out,
+    DevStatus* __restrict__ status, unsigned long long capacity,
+    unsigned long long* __restrict__ total_out) {
+  __shared__ uint32_t lds[8];
+  __shared__ unsigned long long lds4[4];
+  uint32_t carry = 0;
+  unsigned long long total = 0;
+  for (uint32_t c0 = 0; c0 < n; c0 += kScanTile) {
+    const uint32_t base = c0 + threadIdx.x * kScanItems;
+    uint32_t vals[kScanItems];
+    uint32_t s = 0;
+    unsigned long long s64 = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      vals[k] = base + k < n ? in[base + k] : 0u;
+      s += vals[k];
+      s64 += vals[k];
+    }
+    uint32_t tot32;
+    uint32_t run = carry + block_exclusive_scan_u32(s, lds, &tot32);
+    total += block_sum_u64(s64, lds4);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (base + k < n) out[base + k] = run;
+      run += vals[k];
+    }
+    carry += tot32;
+  }
+  if (threadIdx.x == 0 && status != nullptr) {
+    status->pairs_needed = total;
+    status->overflow = total > capacity ? 1u : 0u;
+  }
+  if (threadIdx.x == 0 && total_out != nullptr) *total_out = total;
+}
+
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
                        DevStatus* status, unsigned long long capacity, hipStream_t st,
                        unsigned long long* total_out) {
+  if (n <= kSingleScanMax) {
+    hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kScanThreads), 0, st, in, n, out, status,
+                       capacity, total_out);
+    return hipGetLastError();
+  }
   const uint32_t n_tiles = (n + kScanTile - 1) / kScanTile;
   if (n_tiles > 0)
     hipLaunchKernelGGL(scan_tile_sums_kernel, dim3(n_tiles), dim3(kScanThreads), 0, st, in, n,
@@ -504,6 +564,51 @@ hipError_t launch_compact(const uint32_t* flags, const uint32_t* offsets, uint32
                           uint32_t* list, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(compact_kernel, dim3((n + 255) / 256), dim3(256), 0, st, flags, offsets, n, list);
+  return hipGetLastError();
+}
+
+// First kernel of the binning: zeroes the n_words counters at `words`, and
+// workgroup 0 adds up the per-workgroup counts preprocess left (visible
+// records at partial[k], non-finite primitives at partial[stride + k]) into
+// the status block.
+__global__ void __launch_bounds__(256) bin_prepare_kernel(uint32_t* __restrict__ words,
+                                                          size_t n_words,
+                                                          const uint32_t* __restrict__ partial,
+                                                          uint32_t n_partials, uint32_t stride,
+                                                          DevStatus* __restrict__ status) {
+  const size_t i0 = size_t(blockIdx.x) * 256 + threadIdx.x;
+  for (size_t k = i0; k < n_words; k += size_t(gridDim.x) * 256) words[k] = 0u;
+  if (blockIdx.x != 0) return;
+  __shared__ uint32_t s_sum[2][4];
+  uint32_t vis = 0, nf = 0;
+  for (uint32_t k = threadIdx.x; k < n_partials; k += 256) {
+    vis += partial[k];
+    nf += partial[stride + k];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    vis += __shfl_xor(vis, o, 64);
+    nf += __shfl_xor(nf, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_sum[0][threadIdx.x >> 6] = vis;
+    s_sum[1][threadIdx.x >> 6] = nf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    status->n_visible = s_sum[0][0] + s_sum[0][1] + s_sum[0][2] + s_sum[0][3];
+    status->n_nonfinite = s_sum[1][0] + s_sum[1][1] + s_sum[1][2] + s_sum[1][3];
+  }
+}
+
+hipError_t launch_bin_prepare(uint32_t* words, size_t n_words, const uint32_t* partial,
+                              uint32_t n_partials, uint32_t stride, DevStatus* status,
+                              hipStream_t st) {
+  size_t blocks = (n_words + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(bin_prepare_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, words, n_words,
+                     partial, n_partials, stride, status);
   return hipGetLastError();
 }
 

@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
   }
   if (active) live[i] = visible > 0 ? 1u : 0u;
   // per-workgroup counts (no atomics on a shared word: those serialise across
-  // the chip); sum_partials_kernel adds them into the status block
+  // the chip); the binning's first kernel adds them into the status block
   __shared__ uint32_t s_cnt[2];
   if (threadIdx.x == 0) { s_cnt[0] = 0; s_cnt[1] = 0; }
   __syncthreads();
@@ -77,38 +77,6 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
     partial[blockIdx.x] = s_cnt[1];
     partial[partial_stride + blockIdx.x] = s_cnt[0];
   }
-}
-
-// status->n_visible / n_nonfinite = sums of the n per-workgroup counts.
-__global__ void __launch_bounds__(256) sum_partials_kernel(const uint32_t* __restrict__ partial,
-                                                           uint32_t n, uint32_t stride,
-                                                           DevStatus* __restrict__ status) {
-  __shared__ uint32_t s_sum[2][4];
-  uint32_t vis = 0, nf = 0;
-  for (uint32_t k = threadIdx.x; k < n; k += 256) {
-    vis += partial[k];
-    nf += partial[stride + k];
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    vis += __shfl_xor(vis, o, 64);
-    nf += __shfl_xor(nf, o, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    s_sum[0][threadIdx.x >> 6] = vis;
-    s_sum[1][threadIdx.x >> 6] = nf;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    status->n_visible = s_sum[0][0] + s_sum[0][1] + s_sum[0][2] + s_sum[0][3];
-    status->n_nonfinite = s_sum[1][0] + s_sum[1][1] + s_sum[1][2] + s_sum[1][3];
-  }
-}
-
-hipError_t launch_sum_partials(const uint32_t* partial, uint32_t n, uint32_t stride,
-                               DevStatus* status, hipStream_t st) {
-  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, partial, n, stride, status);
-  return hipGetLastError();
 }
 
 // Thread t runs the adjoint of the t-th live primitive of the compacted list

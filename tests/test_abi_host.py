@@ -57,6 +57,8 @@ def test_ctypes_structs_match_the_header(tmp_path):
                        "n_views", "off_status", "off_records", "off_keys", "off_values",
                        "off_ranges", "off_ncontrib", "off_grad2d"],
         "ubs_status_block": ["pairs_needed", "overflow", "n_nonfinite", "n_visible", "sort_stalled"],
+        "ubs_adam": ["lr_mu_x", "lr_opacity", "lr_scale", "lr_other", "beta1", "beta2", "eps",
+                     "lambda_o", "lambda_s", "lambda_eps", "step"],
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void){"]
     for s, fs in fields.items():
@@ -71,7 +73,7 @@ def test_ctypes_structs_match_the_header(tmp_path):
                                                   check=True).stdout.splitlines())
     py = {"ubs_scene": _lib.UbsScene, "ubs_view": _lib.UbsView, "ubs_tuning": _lib.UbsTuning,
           "ubs_frame": _lib.UbsFrame, "ubs_layout": _lib.UbsLayout,
-          "ubs_status_block": _lib.UbsStatusBlock}
+          "ubs_status_block": _lib.UbsStatusBlock, "ubs_adam": _lib.UbsAdam}
     for s, fs in fields.items():
         assert int(got[s]) == ctypes.sizeof(py[s]), s
         for f in fs:
@@ -169,3 +171,25 @@ def test_empty_frame_is_valid():
     _lib.ubs_preprocess(f.c, 0, 0, lay, 0)
     assert lay.n_records == 0 and lay.n_pixels == 0 and lay.n_tiles == 0
     assert np.isfinite(lay.bytes)
+
+
+@pytest.mark.parametrize("change,code", [
+    (dict(step=0), _lib.UBS_ERR_ARG),
+    (dict(beta1=1.0), _lib.UBS_ERR_ARG),
+    (dict(beta2=-0.1), _lib.UBS_ERR_ARG),
+    (dict(eps=-1.0), _lib.UBS_ERR_ARG),
+    (dict(dim=5), _lib.UBS_ERR_UNSUPPORTED),
+    (dict(dim=8), _lib.UBS_ERR_ARG),
+    (dict(rot=2), _lib.UBS_ERR_ARG),
+    (dict(n=-1), _lib.UBS_ERR_ARG),
+    (dict(params=0), _lib.UBS_ERR_ARG),
+    (dict(n=0, params=0), _lib.UBS_OK),   # nothing to do, nothing launched
+])
+def test_adam_step_argument_errors(change, code):
+    from paper_2510_03312_amd.optim import AdamConfig
+    a = dict(step=1, beta1=0.9, beta2=0.999, eps=1e-15, dim=7, rot=0, n=10, params=0x1000)
+    a.update(change)
+    cfg = AdamConfig(beta1=a["beta1"], beta2=a["beta2"], eps=a["eps"]).to_c(a["step"])
+    got = _lib.ubs_adam_step(cfg, a["dim"], a["rot"], a["n"], a["params"], 0x2000, 0x3000,
+                             0x4000, 0, 0, check=False)
+    assert got == code
