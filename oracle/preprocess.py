@@ -169,6 +169,24 @@ def beta_tilde(b_q: torch.Tensor) -> torch.Tensor:
     return torch.where(b_q < 0, torch.exp(torch.clamp(b_q, max=0.0)), torch.ones_like(b_q))
 
 
+# Ablation variants of Sec. 5.3 (Table "ablation"): the Beta modulation of
+# the conditioning or of the opacity replaced by its Gaussian counterpart.
+NO_BETA_CONDITION = "no_beta_condition"   # diag(bt) = I: Gaussian conditioning
+NO_BETA_OPACITY = "no_beta_opacity"       # o(q) = o exp(-(q - mu_q)^T Sigma_q^-1 (q - mu_q) / 2)
+
+
+def gaussian_opacity(o: torch.Tensor, Sigma_q: torch.Tensor, v: torch.Tensor) -> torch.Tensor:
+    """The "w/o Beta opacity" ablation (Sec. 5.3): the Gaussian conditional
+    opacity of 6DGS/7DGS, o exp(-w.w / 2) with w = Lhat^-1 (q - mu_q).
+    Reading: the paper names the ablation only; this is the Gaussian form the
+    Beta modulation replaces (Sec. 4.3)."""
+    if v.shape[1] == 0:
+        return o
+    Lhat = torch.linalg.cholesky(Sigma_q)
+    w = torch.linalg.solve_triangular(Lhat, v[:, :, None], upper=False)[:, :, 0]
+    return o * torch.exp(-0.5 * (w * w).sum(dim=1))
+
+
 def modulated_opacity(o: torch.Tensor, Sigma_q: torch.Tensor, v: torch.Tensor,
                       b_q: torch.Tensor) -> torch.Tensor:
     """o(q) = o prod_i (1 - tanh(w_i^2))^(4 beta_qi), w = Lhat^-1 (q - mu_q).
@@ -193,13 +211,15 @@ def modulated_opacity(o: torch.Tensor, Sigma_q: torch.Tensor, v: torch.Tensor,
 
 
 def condition(mu_x: torch.Tensor, Sigma: torch.Tensor, v: torch.Tensor,
-              b_q: torch.Tensor):
+              b_q: torch.Tensor, beta_modulated: bool = True):
     """Beta-modulated conditional mean and covariance (Section 4.3).
 
     mu_{x|q} = mu_x + Sigma_xq Sigma_q^-1 diag(bt) (q - mu_q)
     Sigma_{x|q} = Sigma_x - Sigma_xq Sigma_q^-1 diag(bt) Sigma_qx
     Reading: Sigma_{x|q} is symmetrised, (M + M^T)/2, since diag(bt) does not
     commute with Sigma_q^-1 when the modulation differs per dimension.
+    beta_modulated=False is the "w/o Beta condition" ablation (Sec. 5.3):
+    bt = 1, the Gaussian conditional.
     Shapes: mu_x [n,3], Sigma [n,N,N], v [n,C], b_q [n,C].
     """
     C = v.shape[1]
@@ -209,7 +229,8 @@ def condition(mu_x: torch.Tensor, Sigma: torch.Tensor, v: torch.Tensor,
     Sxq = Sigma[:, :3, 3:]
     Sq = Sigma[:, 3:, 3:]
     K = torch.linalg.solve(Sq, Sxq.transpose(-1, -2)).transpose(-1, -2)  # Sxq Sq^-1 (Sq symmetric)
-    D = torch.diag_embed(beta_tilde(b_q))
+    bt = beta_tilde(b_q) if beta_modulated else torch.ones_like(b_q)
+    D = torch.diag_embed(bt)
     KD = K @ D
     mu_c = mu_x + (KD @ v[:, :, None])[:, :, 0]
     M = KD @ Sxq.transpose(-1, -2)
@@ -253,7 +274,8 @@ REC_FIELDS = ("mx", "my", "a", "b", "c", "rho", "o", "beta", "r", "g", "bl", "de
 
 
 def preprocess(params: torch.Tensor, dim: int, rot: int, view,
-               q_override: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
+               q_override: Optional[torch.Tensor] = None,
+               variant: tuple = ()) -> Dict[str, torch.Tensor]:
     """Records for every primitive in one view (differentiable in params).
 
     params: float64 [F][n].  Returns a dict with ``rec`` [n,12] (the fields of
@@ -261,6 +283,7 @@ def preprocess(params: torch.Tensor, dim: int, rot: int, view,
     Culling (Reading): p_z <= 0.2, Sigma' not positive definite, or
     o(q) < 1/255.  rho = 1 - (255 o(q))^(-1/beta_x) is the largest r with
     o(q) (1 - r)^beta_x >= 1/255 (Section 3 Beta kernel, support r < 1).
+    variant: any of NO_BETA_CONDITION, NO_BETA_OPACITY (Sec. 5.3 ablations).
     """
     sl = field_slices(dim, rot)
     C = dim - 3
@@ -273,8 +296,11 @@ def preprocess(params: torch.Tensor, dim: int, rot: int, view,
     v = q - f["mu_q"].T if C > 0 else torch.zeros(n, 0, dtype=F64)
     b_q = f["b_q"].T
     o = f["o"][0]
-    o_q = modulated_opacity(o, Sigma[:, 3:, 3:], v, b_q)
-    mu_c, S_c = condition(mu_x, Sigma, v, b_q)
+    if NO_BETA_OPACITY in variant:
+        o_q = gaussian_opacity(o, Sigma[:, 3:, 3:], v)
+    else:
+        o_q = modulated_opacity(o, Sigma[:, 3:, 3:], v, b_q)
+    mu_c, S_c = condition(mu_x, Sigma, v, b_q, beta_modulated=NO_BETA_CONDITION not in variant)
     mean2d, Sp, depth = project(mu_c, S_c, view)
     det = Sp[:, 0, 0] * Sp[:, 1, 1] - Sp[:, 0, 1] * Sp[:, 1, 0]
     valid = (depth > NEAR_PLANE) & (det > 0) & (Sp[:, 0, 0] > 0) & (Sp[:, 1, 1] > 0) \

@@ -61,7 +61,8 @@ def _amb_records(out: dict, amb: np.ndarray, rec: np.ndarray) -> np.ndarray:
 
 def render(params: np.ndarray, dim: int, rot: int, view, *, d_image: Optional[np.ndarray] = None,
            d_tfinal: Optional[np.ndarray] = None, l1_target: Optional[np.ndarray] = None,
-           rows=None, bands=raster.DEFAULT_BANDS, record_f32: bool = False):
+           rows=None, bands=raster.DEFAULT_BANDS, record_f32: bool = False,
+           variant: tuple = ()):
     """Render one view in float64.
 
     params: [F][n] (any float dtype; promoted to float64).  If ``d_image``
@@ -77,7 +78,7 @@ def render(params: np.ndarray, dim: int, rot: int, view, *, d_image: Optional[np
     """
     want_grad = d_image is not None or l1_target is not None
     P = torch.tensor(np.asarray(params, dtype=np.float64), requires_grad=want_grad)
-    out = pp.preprocess(P, dim, rot, view)
+    out = pp.preprocess(P, dim, rot, view, variant=variant)
     rec = out["rec"].detach().numpy()
     if record_f32:
         rec = rec.astype(np.float32).astype(np.float64)
@@ -120,9 +121,9 @@ def _abs_chain(P: torch.Tensor, rec: torch.Tensor, d_abs: np.ndarray) -> np.ndar
 
 
 def loss_value(params: np.ndarray, dim: int, rot: int, view, weight_image: np.ndarray,
-               weight_t: Optional[np.ndarray] = None) -> float:
+               weight_t: Optional[np.ndarray] = None, variant: tuple = ()) -> float:
     """Scalar <weight_image, image> + <weight_t, T_final> for finite differences."""
-    r = render(params, dim, rot, view)
+    r = render(params, dim, rot, view, variant=variant)
     v = float((r["image"] * weight_image).sum())
     if weight_t is not None:
         v += float((r["t_final"] * weight_t).sum())

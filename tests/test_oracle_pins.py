@@ -539,11 +539,11 @@ def test_binning_keys_sort_and_ranges():
 
 
 # --------------------------------------------------------------------- gradients
-def _fd_check(P, dim, rot, view, rng, n_check=40, h_rel=1e-6):
+def _fd_check(P, dim, rot, view, rng, n_check=40, h_rel=1e-6, variant=()):
     W, H = view.width, view.height
     wimg = rng.normal(size=(H, W, 3))
     wt = rng.normal(size=(H, W))
-    res = render.render(P, dim, rot, view, d_image=wimg, d_tfinal=wt)
+    res = render.render(P, dim, rot, view, d_image=wimg, d_tfinal=wt, variant=variant)
     g = res["dparams"]
     F, n = P.shape
     scale = np.abs(g).max()
@@ -560,8 +560,8 @@ def _fd_check(P, dim, rot, view, rng, n_check=40, h_rel=1e-6):
             Pp, Pm = P.copy(), P.copy()
             Pp[f, i] += hh
             Pm[f, i] -= hh
-            vals.append((render.loss_value(Pp, dim, rot, view, wimg, wt)
-                         - render.loss_value(Pm, dim, rot, view, wimg, wt)) / (2 * hh))
+            vals.append((render.loss_value(Pp, dim, rot, view, wimg, wt, variant)
+                         - render.loss_value(Pm, dim, rot, view, wimg, wt, variant)) / (2 * hh))
         if abs(vals[0] - vals[1]) > 1e-6 * max(abs(vals[1]), 1e-3 * scale):
             continue   # a threshold (skip/stop/clamp/kink) lies within h: discard
         assert abs(g[f, i] - vals[1]) <= 1e-5 * max(abs(vals[1]), 1e-3 * scale), (f, i, g[f, i], vals)
