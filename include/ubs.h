@@ -130,6 +130,11 @@ typedef struct {
 #define UBS_TUNE_PERSISTENT 1u  /* raster through a persistent grid that takes
                                    tiles from a work queue (16 wavefronts per CU) */
 #define UBS_TUNE_PRE_FP32 2u    /* per-primitive math in float32 (default float64) */
+/* Ablation variants of Section 5.3 (default: both Beta modulations on). */
+#define UBS_TUNE_NO_BETA_COND 4u     /* "w/o Beta condition": conditioning with
+                                        diag(bt) = I (the Gaussian conditional) */
+#define UBS_TUNE_NO_BETA_OPACITY 8u  /* "w/o Beta opacity": o(q) = o exp(-w.w/2),
+                                        the Gaussian conditional opacity */
 typedef struct {
   int32_t tile_w, tile_h;
   int32_t batch_depth;

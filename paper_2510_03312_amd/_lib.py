@@ -25,6 +25,8 @@ UBS_ROT_QUAT = 0
 UBS_ROT_SKEW = 1
 UBS_TUNE_PERSISTENT = 1
 UBS_TUNE_PRE_FP32 = 2
+UBS_TUNE_NO_BETA_COND = 4
+UBS_TUNE_NO_BETA_OPACITY = 8
 
 EXPORTS = ("ubs_preprocess", "ubs_bin_sort", "ubs_render_fwd", "ubs_render_bwd",
            "ubs_adam_step", "ubs_param_count", "ubs_abi_version")

@@ -137,6 +137,7 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
     d.dim = S.dim;
     d.rot = S.rot;
     d.F = param_rows(S.dim - 3, S.rot).F;
+    d.variant = tu.flags & (UBS_TUNE_NO_BETA_COND | UBS_TUNE_NO_BETA_OPACITY);
     d.prim_base = int64_t(n_prims);
     n_prims += uint64_t(S.n);
     n_grad_compact = n_grad_compact > uint64_t(d.F) * uint64_t(S.n) ? n_grad_compact

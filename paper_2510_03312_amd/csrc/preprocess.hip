@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
   if (active) {
     load_raw<C, ROT>(S.params, S.n, i, r);
     finite = r.finite;
-    geo_forward<T, C, ROT>(r, g);
+    geo_forward<T, C, ROT>(r, g, S.variant);
   }
   uint32_t visible = 0;
   for (int v = 0; v < n_views; ++v) {
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int sce
   Raw<C, ROT> r;
   load_raw<C, ROT>(S.params, S.n, i, r);
   Geo<T, C, ROT> g;
-  geo_forward<T, C, ROT>(r, g);
+  geo_forward<T, C, ROT>(r, g, S.variant);
   GeoGrad<T, C> G;
   geograd_zero<T, C>(G);
   for (int v = 0; v < n_views; ++v) {

@@ -102,10 +102,15 @@ struct Geo {
   T Sxq[3][Cdim<C>::V];
   T Lh[Cdim<C>::V][Cdim<C>::V];      // chol(Sigma_q)
   T Li[Cdim<C>::V][Cdim<C>::V];      // Lh^-1 (lower)
-  T bt[Cdim<C>::V];                  // min(exp(b_q), 1)
-  T e[Cdim<C>::V];                   // 4 exp(b_q)
+  T bt[Cdim<C>::V];                  // min(exp(b_q), 1); 1 without the Beta condition
+  T e[Cdim<C>::V];                   // 4 exp(b_q); 1 without the Beta opacity
   bool ok;
+  bool beta_cond, beta_opacity;      // the Beta modulations in use (Sec. 5.3 ablations)
 };
+
+// Ablation variants (Sec. 5.3), bits of the frame's tuning flags.
+constexpr uint32_t kVarNoBetaCond = UBS_TUNE_NO_BETA_COND;
+constexpr uint32_t kVarNoBetaOpacity = UBS_TUNE_NO_BETA_OPACITY;
 
 // Activated L_q (lower triangular, diagonal exp of the stored log scale).
 template <typename T, int C, int ROT>
@@ -114,8 +119,11 @@ __device__ __forceinline__ T lq_entry(const Raw<C, ROT>& r, int a, int b) {
 }
 
 template <typename T, int C, int ROT>
-__device__ __forceinline__ void geo_forward(const Raw<C, ROT>& r, Geo<T, C, ROT>& g) {
+__device__ __forceinline__ void geo_forward(const Raw<C, ROT>& r, Geo<T, C, ROT>& g,
+                                            uint32_t variant) {
   g.ok = r.finite;
+  g.beta_cond = (variant & kVarNoBetaCond) == 0;
+  g.beta_opacity = (variant & kVarNoBetaOpacity) == 0;
   struct { T R[3][3]; } gr;
   auto& R = gr.R;
   if (ROT == UBS_ROT_QUAT) {
@@ -210,8 +218,8 @@ __device__ __forceinline__ void geo_forward(const Raw<C, ROT>& r, Geo<T, C, ROT>
 #pragma unroll
     for (int k = 0; k < C; ++k) {
       T eb = m_exp<T>(T(r.bq[k]));
-      g.bt[k] = r.bq[k] < 0.0f ? eb : T(1);
-      g.e[k] = T(4) * eb;
+      g.bt[k] = (g.beta_cond && r.bq[k] < 0.0f) ? eb : T(1);
+      g.e[k] = g.beta_opacity ? T(4) * eb : T(1);
     }
   }
 }
@@ -275,7 +283,10 @@ __device__ __forceinline__ void view_forward(const Raw<C, ROT>& r, const Geo<T, 
       for (int k = 0; k <= i; ++k) acc += g.Li[i][k] * s.v[k];
       s.w[i] = acc;
       T x = acc * acc;
-      s.ell[i] = T(0.69314718055994530942) - T(2) * x - m_log1p<T>(m_exp<T>(T(-2) * x));
+      // Gaussian opacity (ablation): e = 1 and ell = -w^2 / 2
+      s.ell[i] = g.beta_opacity
+                     ? T(0.69314718055994530942) - T(2) * x - m_log1p<T>(m_exp<T>(T(-2) * x))
+                     : T(-0.5) * x;
       lsum += g.e[i] * s.ell[i];
     }
     oq = T(r.o) * m_exp<T>(lsum);
@@ -553,10 +564,14 @@ __device__ __forceinline__ void view_backward(const Raw<C, ROT>& r, const Geo<T,
     T gw[Cdim<C>::V];
 #pragma unroll
     for (int i = 0; i < C; ++i) {
-      G.bq[i] += goq * s.oq * s.ell[i] * g.e[i];
-      T x = s.w[i] * s.w[i];
-      T th = m_tanh<T>(x);
-      gw[i] = goq * s.oq * g.e[i] * (-(T(1) + th)) * T(2) * s.w[i];
+      if (g.beta_opacity) {
+        G.bq[i] += goq * s.oq * s.ell[i] * g.e[i];
+        T x = s.w[i] * s.w[i];
+        T th = m_tanh<T>(x);
+        gw[i] = goq * s.oq * g.e[i] * (-(T(1) + th)) * T(2) * s.w[i];
+      } else {
+        gw[i] = -goq * s.oq * s.w[i];   // d(-w^2/2)/dw; no b_q dependence
+      }
     }
     // w = Li v:  g_v += Li^T gw ; G_Lh += -tril((Li^T gw) w^T)
     T ut[Cdim<C>::V];
@@ -713,7 +728,7 @@ __device__ __forceinline__ void geo_backward(const Raw<C, ROT>& r, const Geo<T, 
     for (int k = 0; k < C; ++k) {
       out[pr.mu_q + k] = float(G.muq[k]);
       T gbq = G.bq[k];
-      if (r.bq[k] < 0.0f) gbq += G.bt[k] * g.bt[k];
+      if (g.beta_cond && r.bq[k] < 0.0f) gbq += G.bt[k] * g.bt[k];
       out[pr.b_q + k] = float(gbq);
     }
   }

@@ -40,7 +40,7 @@ struct DevScene {
   float* dparams;
   int64_t n;
   int32_t dim, rot, F;
-  int32_t _pad;
+  uint32_t variant;    // UBS_TUNE_NO_BETA_* bits of the frame (Sec. 5.3 ablations)
   int64_t prim_base;   // first entry of this scene in per-primitive tables
 };
 
