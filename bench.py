@@ -64,6 +64,8 @@ WORKLOADS = {
                      "resolution in one batched frame, autotuned, forward+backward, L1 loss"),
     "adam": ("headline", "optimiser step (regularisers, Adam, spatial noise) over the parameters "
                          "of 1,000,000 7-D primitives (45 rows)"),
+    "relocate": ("headline", "relocation of dead primitives (opacity < 0.005, 30% of 1,000,000 "
+                             "7-D primitives) to live ones drawn by opacity"),
 }
 
 
@@ -433,6 +435,58 @@ def run_adam(args, name, desc):
     }
 
 
+def run_relocate(args, name, desc):
+    """Relocation alone, on a fresh copy of the same state each step (the
+    copy is outside the timed region: one stream, events around the call)."""
+    import numpy as np
+    import torch
+    from paper_2510_03312_amd.optim import relocate
+    from oracle.preprocess import field_slices  # noqa: F401  (layout only)
+    from synth import make_config
+
+    cfg = make_config(name)
+    sc = cfg["scenes"][0]
+    dev = torch.device("cuda:0")
+    F, n = sc.params.shape
+    P = sc.params.copy()
+    rng = np.random.default_rng(7)
+    o_row = F - 4
+    P[o_row] = np.where(rng.uniform(size=n) < 0.3, 0.001, P[o_row]).astype(np.float32)
+    base = torch.from_numpy(P).to(dev)
+    params = base.clone()
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    u = torch.from_numpy(rng.uniform(size=n)).to(dev)
+    total = 0.0
+    n_dead = 0
+    for k in range(args.warmup + args.steps):
+        params.copy_(base)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, nd = relocate(params, m, v, u, sc.dim, sc.rot)
+        e1.record()
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            total += e0.elapsed_time(e1)
+        n_dead = int(nd.item())
+    ms = total / args.steps
+    # every row read once, cdf / flags / scans, and per dead slot its source
+    # column read and its own column plus both columns' moments written
+    nbytes = 4.0 * F * n + 40.0 * n + n_dead * (4.0 * F * 6 + 24.0)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {
+        "metric": "relocation passes/s (1M 7-D prims, 30% dead)", "value": round(1000.0 / ms, 2),
+        "unit": "passes/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": desc, "primitives": n, "rows": F, "dead": n_dead},
+        "roofline": {"bound": "hbm", "kernel": "relocate", "achieved": round(gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_step": nbytes},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -458,6 +512,8 @@ def main() -> int:
     log(f"[bench] workload {args.workload}")
     if args.workload == "adam":
         res = run_adam(args, name, desc)
+    elif args.workload == "relocate":
+        res = run_relocate(args, name, desc)
     elif name in ("cfg3", "cfg4"):
         res = run_batched(args, name, desc)
     else:

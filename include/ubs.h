@@ -329,6 +329,35 @@ ubs_status ubs_adam_step(const ubs_adam* cfg, int32_t dim, int32_t rot, int64_t 
                          float* params, const float* dparams, float* m, float* v,
                          const float* noise, void* stream);
 
+/*
+ * ubs_relocate -- relocation of dead primitives, in place.
+ * Paper: Section 4.5 ("Densification": cloned opacity o' = 1 - (1 - o)^(1/N);
+ * the MCMC primitive management adopted from Deformable Beta Splatting).
+ * A primitive is dead if its opacity is below o_min (0.005 by default) or a
+ * parameter is not finite; the k-th dead primitive (in index order) copies
+ * the first live j whose running opacity sum exceeds uniforms[k] times the
+ * total (float64; if the product rounds to the total, the last live
+ * primitive); a live primitive picked N - 1 times and its N - 1 copies all
+ * get o' = 1 - (1 - o_j)^(1/N), every other parameter is copied, and the
+ * Adam moments m, v of all of them are zeroed.  Nothing moves if there is no
+ * live or no dead primitive.
+ * params, m, v: device float32 [F][n] (ubs_scene layout), read and written.
+ * uniforms: device float64 [n], values in [0, 1) (the first n_dead are used).
+ * ws: device workspace of at least *ws_bytes_needed bytes; ws == NULL is a
+ * size query (writes *ws_bytes_needed, which must then be non-NULL).
+ * targets_out: optional device uint32 [n], the pick of every dead slot (the
+ * first n_dead entries).  n_dead_out: optional device uint64, the number of
+ * dead slots.  Asynchronous on stream.  Errors: UBS_ERR_ARG (bad dim/rot,
+ * n < 0, o_min < 0 or NaN, a NULL buffer with n > 0), UBS_ERR_UNSUPPORTED
+ * (dim 4/5, n >= 2^31), UBS_ERR_CAPACITY (ws_bytes too small), UBS_ERR_HIP.
+ * The pick is exact for n < 2^22 and opacities <= 1: every running sum of
+ * float32 opacities >= o_min is then representable in float64.
+ */
+ubs_status ubs_relocate(int32_t dim, int32_t rot, int64_t n, float* params, float* m, float* v,
+                        const double* uniforms, float o_min, void* ws, uint64_t ws_bytes,
+                        uint64_t* ws_bytes_needed, uint32_t* targets_out, uint64_t* n_dead_out,
+                        void* stream);
+
 /* Number of parameter rows F for a scene (0 for an unsupported dim/rot). */
 int32_t ubs_param_count(int32_t dim, int32_t rot);
 

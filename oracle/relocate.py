@@ -10,7 +10,8 @@ Steps, in the paper's terms:
   2. every dead slot picks a live primitive with probability proportional to
      its opacity (the random numbers are inputs: uniform u_k in [0, 1) for
      the k-th dead slot in index order), by inverse-CDF sampling over the
-     running sum of the live opacities;
+     running sum of the live opacities (if u_k * total rounds to the total,
+     the last live primitive);
   3. a live primitive picked by N - 1 dead slots becomes N identical copies
      (itself and the slots), each with opacity o' = 1 - (1 - o)^(1/N), so
      that the N copies composite to the original opacity (the paper's
@@ -59,6 +60,8 @@ def relocate(params: np.ndarray, m: np.ndarray, v: np.ndarray, uniforms: np.ndar
     total = cdf[-1]
     x = np.asarray(uniforms[:dead.size], dtype=np.float64) * total
     targets = np.searchsorted(cdf, x, side="right")
+    # u within an ulp of 1 can round x up to the total: the last live one
+    targets[targets >= cdf.size] = np.searchsorted(cdf, total, side="left")
     copies = 1 + np.bincount(targets, minlength=P.shape[1])
     picked = np.flatnonzero(copies > 1)
     o_new = cloned_opacity(o[picked], copies[picked])

@@ -29,7 +29,7 @@ UBS_TUNE_NO_BETA_COND = 4
 UBS_TUNE_NO_BETA_OPACITY = 8
 
 EXPORTS = ("ubs_preprocess", "ubs_bin_sort", "ubs_render_fwd", "ubs_render_bwd",
-           "ubs_adam_step", "ubs_param_count", "ubs_abi_version")
+           "ubs_adam_step", "ubs_relocate", "ubs_param_count", "ubs_abi_version")
 
 
 class UbsScene(ctypes.Structure):
@@ -108,6 +108,10 @@ def load() -> ctypes.CDLL:
         L.ubs_adam_step.argtypes = [POINTER(UbsAdam), c_int32, c_int32, c_int64, c_void_p,
                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
         L.ubs_adam_step.restype = c_int32
+        L.ubs_relocate.argtypes = [c_int32, c_int32, c_int64, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_float, c_void_p, c_uint64, POINTER(c_uint64),
+                                   c_void_p, c_void_p, c_void_p]
+        L.ubs_relocate.restype = c_int32
         L.ubs_param_count.argtypes = [c_int32, c_int32]
         L.ubs_param_count.restype = c_int32
         L.ubs_abi_version.argtypes = []
@@ -154,6 +158,18 @@ def ubs_adam_step(cfg: UbsAdam, dim: int, rot: int, n: int, params: int, dparams
     code = load().ubs_adam_step(ctypes.byref(cfg), dim, rot, n, params, dparams, m, v, noise,
                                 stream)
     return _check("ubs_adam_step", code) if check else code
+
+
+def ubs_relocate(dim: int, rot: int, n: int, params: int, m: int, v: int, uniforms: int,
+                 o_min: float, ws: int, ws_bytes: int, targets_out: int, n_dead_out: int,
+                 stream: int, check: bool = True):
+    """Returns the workspace bytes needed when ws == 0 (size query), else the code."""
+    need = c_uint64(0)
+    code = load().ubs_relocate(dim, rot, n, params, m, v, uniforms, o_min, ws, ws_bytes,
+                               ctypes.byref(need), targets_out, n_dead_out, stream)
+    if check:
+        _check("ubs_relocate", code)
+    return int(need.value) if not ws else code
 
 
 def ubs_param_count(dim: int, rot: int) -> int:

@@ -1,0 +1,251 @@
+// Relocation of dead primitives (Sec. 4.5 cloning rule with the MCMC
+// primitive management the paper adopts): every primitive whose opacity is
+// below o_min (or whose parameters are not finite) copies a live primitive
+// picked with probability proportional to opacity, and the N copies of a
+// picked primitive (itself included) share o' = 1 - (1 - o)^(1/N).
+//
+//   weights   per primitive: w = o if live else 0, the dead flag, o kept
+//   cdf       inclusive float64 scan of w (exact: live opacities are
+//             float32 values >= o_min, so every partial sum is a multiple
+//             of 2^-31 below 2^22 for n < 2^22; the order of the additions
+//             does not matter)
+//   dead      exclusive scan of the dead flags and compaction: the dead
+//             slots in index order
+//   sample    slot k: first j with cdf[j] > u_k * total (float64), one
+//             atomic per slot on the copy count of j
+//   apply     slot k copies column j, both get o'; their Adam moments reset
+#include <cmath>
+
+#include "ubs_internal.hpp"
+
+namespace ubs {
+
+hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
+                       DevStatus* status, unsigned long long capacity, hipStream_t st,
+                       unsigned long long* total_out);
+hipError_t launch_compact(const uint32_t* flags, const uint32_t* offsets, uint32_t n,
+                          uint32_t* list, hipStream_t st);
+
+constexpr int kRelThreads = 256;
+constexpr int kRelItems = 16;
+constexpr int kRelTile = kRelThreads * kRelItems;
+
+struct RelocLayout {
+  uint64_t cdf, o_keep, dead, offs, list, targets, counts, sums_u32, sums_f64, n_dead, bytes;
+  uint32_t n_tiles;
+};
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+static RelocLayout reloc_layout(int64_t n) {
+  RelocLayout L{};
+  const uint64_t un = uint64_t(n);
+  L.n_tiles = uint32_t((un + kRelTile - 1) / kRelTile);
+  uint64_t off = 0;
+  auto take = [&](uint64_t b) { const uint64_t o = off; off = align256(off + b); return o; };
+  L.cdf = take(8 * un);
+  L.o_keep = take(4 * un);
+  L.dead = take(4 * un);
+  L.offs = take(4 * un);
+  L.list = take(4 * un);
+  L.targets = take(4 * un);
+  L.counts = take(4 * un);
+  L.sums_u32 = take(4 * (uint64_t(L.n_tiles) + 1));
+  L.sums_f64 = take(8 * (uint64_t(L.n_tiles) + 1));
+  L.n_dead = take(8);
+  L.bytes = off;
+  return L;
+}
+
+__global__ void __launch_bounds__(kRelThreads) reloc_weights_kernel(
+    const float* __restrict__ params, int64_t n, int F, int o_row, float o_min,
+    double* __restrict__ w, float* __restrict__ o_keep, uint32_t* __restrict__ dead,
+    uint32_t* __restrict__ counts) {
+  const int64_t i = int64_t(blockIdx.x) * kRelThreads + threadIdx.x;
+  if (i >= n) return;
+  bool finite = true;
+  for (int r = 0; r < F; ++r) finite = finite && isfinite(params[int64_t(r) * n + i]);
+  const float o = params[int64_t(o_row) * n + i];
+  const bool live = finite && o >= o_min;
+  w[i] = live ? double(o) : 0.0;
+  o_keep[i] = o;
+  dead[i] = live ? 0u : 1u;
+  counts[i] = 0u;
+}
+
+// Inclusive float64 scan: per-tile sums, one workgroup scans them, apply.
+__device__ __forceinline__ double wg_inclusive_scan_f64(double v, double* lds4, double* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds4[wave] = x;
+  __syncthreads();
+  double base = 0.0, tot = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k < wave) base += lds4[k];
+    tot += lds4[k];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x;
+}
+
+__global__ void __launch_bounds__(kRelThreads) cdf_tile_sums_kernel(const double* __restrict__ w,
+                                                                    int64_t n,
+                                                                    double* __restrict__ sums) {
+  __shared__ double lds4[4];
+  const int64_t base = int64_t(blockIdx.x) * kRelTile + int64_t(threadIdx.x) * kRelItems;
+  double s = 0.0;
+  for (int k = 0; k < kRelItems; ++k)
+    if (base + k < n) s += w[base + k];
+  double tot;
+  wg_inclusive_scan_f64(s, lds4, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kRelThreads) cdf_sums_scan_kernel(double* __restrict__ sums,
+                                                                    uint32_t n_tiles) {
+  __shared__ double lds4[4];
+  double carry = 0.0;
+  for (uint32_t b = 0; b < n_tiles; b += kRelThreads) {
+    const uint32_t i = b + threadIdx.x;
+    const double v = i < n_tiles ? sums[i] : 0.0;
+    double tot;
+    const double incl = wg_inclusive_scan_f64(v, lds4, &tot);
+    if (i < n_tiles) sums[i] = carry + incl - v;   // exclusive
+    carry += tot;
+  }
+}
+
+__global__ void __launch_bounds__(kRelThreads) cdf_apply_kernel(double* __restrict__ w, int64_t n,
+                                                                const double* __restrict__ sums) {
+  __shared__ double lds4[4];
+  const int64_t base = int64_t(blockIdx.x) * kRelTile + int64_t(threadIdx.x) * kRelItems;
+  double vals[kRelItems];
+  double s = 0.0;
+  for (int k = 0; k < kRelItems; ++k) {
+    vals[k] = base + k < n ? w[base + k] : 0.0;
+    s += vals[k];
+  }
+  double tot;
+  double run = sums[blockIdx.x] + wg_inclusive_scan_f64(s, lds4, &tot) - s;
+  for (int k = 0; k < kRelItems; ++k) {
+    run += vals[k];
+    if (base + k < n) w[base + k] = run;
+  }
+}
+
+// First index j with cdf[j] > x (strict) or >= x, cdf non-decreasing; n if none.
+template <bool STRICT>
+__device__ __forceinline__ int64_t first_index(const double* __restrict__ cdf, int64_t n, double x) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    const bool past = STRICT ? cdf[mid] > x : cdf[mid] >= x;
+    if (past) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+// Dead slot k picks the first j with cdf[j] > u_k * total; when the product
+// rounds to the total itself (u within an ulp of 1) there is none, and the
+// pick is the last live primitive (the first j with cdf[j] >= total).
+__global__ void __launch_bounds__(kRelThreads) reloc_sample_kernel(
+    const double* __restrict__ cdf, int64_t n, const unsigned long long* __restrict__ n_dead,
+    const double* __restrict__ uniforms, uint32_t* __restrict__ targets,
+    uint32_t* __restrict__ counts) {
+  const int64_t k = int64_t(blockIdx.x) * kRelThreads + threadIdx.x;
+  const double total = cdf[n - 1];
+  if (k >= int64_t(*n_dead) || !(total > 0.0)) return;
+  int64_t j = first_index<true>(cdf, n, uniforms[k] * total);
+  if (j >= n) j = first_index<false>(cdf, n, total);
+  targets[k] = uint32_t(j);
+  atomicAdd(&counts[j], 1u);
+}
+
+__global__ void copy_count_kernel(const unsigned long long* __restrict__ src,
+                                  uint64_t* __restrict__ dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
+__global__ void __launch_bounds__(kRelThreads) reloc_apply_kernel(
+    float* __restrict__ params, float* __restrict__ m, float* __restrict__ v, int64_t n, int F,
+    int o_row, const double* __restrict__ cdf, const float* __restrict__ o_keep,
+    const uint32_t* __restrict__ list, const unsigned long long* __restrict__ n_dead,
+    const uint32_t* __restrict__ targets, const uint32_t* __restrict__ counts,
+    uint32_t* __restrict__ targets_out) {
+  const int64_t k = int64_t(blockIdx.x) * kRelThreads + threadIdx.x;
+  if (k >= int64_t(*n_dead) || !(cdf[n - 1] > 0.0)) return;
+  const int64_t d = list[k];
+  const int64_t j = targets[k];
+  const double copies = double(counts[j]) + 1.0;
+  const float o_new = float(1.0 - pow(1.0 - double(o_keep[j]), 1.0 / copies));
+  for (int r = 0; r < F; ++r) {
+    const int64_t row = int64_t(r) * n;
+    params[row + d] = r == o_row ? o_new : params[row + j];
+    m[row + d] = 0.0f;
+    v[row + d] = 0.0f;
+    m[row + j] = 0.0f;   // every copy of j writes the same zeros and o'
+    v[row + j] = 0.0f;
+  }
+  params[int64_t(o_row) * n + j] = o_new;
+  if (targets_out) targets_out[k] = uint32_t(j);
+}
+
+}  // namespace ubs
+
+using namespace ubs;
+
+extern "C" ubs_status ubs_relocate(int32_t dim, int32_t rot, int64_t n, float* params, float* m,
+                                   float* v, const double* uniforms, float o_min, void* ws,
+                                   uint64_t ws_bytes, uint64_t* ws_bytes_needed,
+                                   uint32_t* targets_out, uint64_t* n_dead_out, void* stream) {
+  if (dim < 3 || dim > 7 || (rot != UBS_ROT_QUAT && rot != UBS_ROT_SKEW) || n < 0)
+    return UBS_ERR_ARG;
+  if (dim == 4 || dim == 5) return UBS_ERR_UNSUPPORTED;
+  if (n > (int64_t(1) << 31) - 1) return UBS_ERR_UNSUPPORTED;
+  if (!(o_min >= 0.0f)) return UBS_ERR_ARG;
+  const RelocLayout L = reloc_layout(n);
+  if (!ws) {
+    if (!ws_bytes_needed) return UBS_ERR_ARG;
+    *ws_bytes_needed = L.bytes;
+    return UBS_OK;
+  }
+  if (ws_bytes < L.bytes) return UBS_ERR_CAPACITY;
+  if (n == 0) return UBS_OK;
+  if (!params || !m || !v || !uniforms) return UBS_ERR_ARG;
+  const ParamRows pr = param_rows(dim - 3, rot);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  double* cdf = reinterpret_cast<double*>(base + L.cdf);
+  float* o_keep = reinterpret_cast<float*>(base + L.o_keep);
+  uint32_t* dead = reinterpret_cast<uint32_t*>(base + L.dead);
+  uint32_t* offs = reinterpret_cast<uint32_t*>(base + L.offs);
+  uint32_t* list = reinterpret_cast<uint32_t*>(base + L.list);
+  uint32_t* targets = reinterpret_cast<uint32_t*>(base + L.targets);
+  uint32_t* counts = reinterpret_cast<uint32_t*>(base + L.counts);
+  double* sums = reinterpret_cast<double*>(base + L.sums_f64);
+  unsigned long long* n_dead = reinterpret_cast<unsigned long long*>(base + L.n_dead);
+  const unsigned blocks = unsigned((n + kRelThreads - 1) / kRelThreads);
+  hipLaunchKernelGGL(reloc_weights_kernel, dim3(blocks), dim3(kRelThreads), 0, st, params, n,
+                     pr.F, pr.o, o_min, cdf, o_keep, dead, counts);
+  hipLaunchKernelGGL(cdf_tile_sums_kernel, dim3(L.n_tiles), dim3(kRelThreads), 0, st, cdf, n, sums);
+  hipLaunchKernelGGL(cdf_sums_scan_kernel, dim3(1), dim3(kRelThreads), 0, st, sums, L.n_tiles);
+  hipLaunchKernelGGL(cdf_apply_kernel, dim3(L.n_tiles), dim3(kRelThreads), 0, st, cdf, n, sums);
+  if (launch_scan(dead, uint32_t(n), reinterpret_cast<uint32_t*>(base + L.sums_u32), offs,
+                  nullptr, 0ull, st, n_dead) != hipSuccess)
+    return UBS_ERR_HIP;
+  if (launch_compact(dead, offs, uint32_t(n), list, st) != hipSuccess) return UBS_ERR_HIP;
+  hipLaunchKernelGGL(reloc_sample_kernel, dim3(blocks), dim3(kRelThreads), 0, st, cdf, n, n_dead,
+                     uniforms, targets, counts);
+  hipLaunchKernelGGL(reloc_apply_kernel, dim3(blocks), dim3(kRelThreads), 0, st, params, m, v, n,
+                     pr.F, pr.o, cdf, o_keep, list, n_dead, targets, counts, targets_out);
+  if (n_dead_out)
+    hipLaunchKernelGGL(copy_count_kernel, dim3(1), dim3(64), 0, st, n_dead, n_dead_out);
+  return hipGetLastError() == hipSuccess ? UBS_OK : UBS_ERR_HIP;
+}

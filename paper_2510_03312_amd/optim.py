@@ -1,6 +1,7 @@
-"""Optimiser step (``ubs_adam_step``): the Sec. 4.5 regularisers and spatial
+"""Optimiser step (``ubs_adam_step``: the Sec. 4.5 regularisers and spatial
 noise, Adam with the Sec. 5.1 per-group learning rates, in one kernel over a
-scene's [F][n] parameters.  Argument marshalling only."""
+scene's [F][n] parameters) and the relocation of dead primitives
+(``ubs_relocate``: Sec. 4.5 cloning rule).  Argument marshalling only."""
 from __future__ import annotations
 
 from dataclasses import dataclass
@@ -52,3 +53,28 @@ def adam_step(params: torch.Tensor, dparams: torch.Tensor, m: torch.Tensor, v: t
     _lib.ubs_adam_step(cfg.to_c(step), dim, rot, n, params.data_ptr(), dparams.data_ptr(),
                        m.data_ptr(), v.data_ptr(), 0 if noise is None else noise.data_ptr(),
                        stream)
+
+
+def relocate(params: torch.Tensor, m: torch.Tensor, v: torch.Tensor, uniforms: torch.Tensor,
+             dim: int, rot: int, o_min: float = 0.005):
+    """Relocates dead primitives in place (params, m, v) on the current
+    stream; uniforms: float64 [n] in [0, 1).  Returns (targets, n_dead):
+    device tensors, the pick of each dead slot (first n_dead entries) and
+    the number of dead slots."""
+    F = _lib.ubs_param_count(dim, rot)
+    if F <= 0:
+        raise ValueError(f"unsupported dim {dim} / rot {rot}")
+    n = params.shape[1] if params.dim() == 2 else -1
+    for name, t in (("params", params), ("m", m), ("v", v)):
+        _check_tensor(name, t, (F, n))
+    if uniforms.dtype != torch.float64 or not uniforms.is_cuda or tuple(uniforms.shape) != (n,):
+        raise ValueError("uniforms: expected a float64 device tensor of shape (n,)")
+    need = _lib.ubs_relocate(dim, rot, n, 0, 0, 0, 0, o_min, 0, 0, 0, 0, 0)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=params.device)
+    targets = torch.zeros(max(n, 1), dtype=torch.int32, device=params.device)
+    n_dead = torch.zeros(1, dtype=torch.int64, device=params.device)
+    stream = torch.cuda.current_stream().cuda_stream
+    _lib.ubs_relocate(dim, rot, n, params.data_ptr(), m.data_ptr(), v.data_ptr(),
+                      uniforms.data_ptr(), o_min, ws.data_ptr(), ws.numel(), targets.data_ptr(),
+                      n_dead.data_ptr(), stream)
+    return targets, n_dead

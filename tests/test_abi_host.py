@@ -193,3 +193,18 @@ def test_adam_step_argument_errors(change, code):
     got = _lib.ubs_adam_step(cfg, a["dim"], a["rot"], a["n"], a["params"], 0x2000, 0x3000,
                              0x4000, 0, 0, check=False)
     assert got == code
+
+
+def test_relocate_size_query_and_errors():
+    need = _lib.ubs_relocate(7, 0, 1000, 0, 0, 0, 0, 0.005, 0, 0, 0, 0, 0)
+    assert need >= 1000 * (8 + 4 * 6)
+    assert _lib.ubs_relocate(7, 0, 0, 0, 0, 0, 0, 0.005, 0, 0, 0, 0, 0) >= 0
+    bad = [dict(dim=5, code=_lib.UBS_ERR_UNSUPPORTED), dict(rot=3, code=_lib.UBS_ERR_ARG),
+           dict(n=-1, code=_lib.UBS_ERR_ARG), dict(o_min=-1.0, code=_lib.UBS_ERR_ARG),
+           dict(ws_bytes=16, code=_lib.UBS_ERR_CAPACITY), dict(params=0, code=_lib.UBS_ERR_ARG)]
+    for b in bad:
+        a = dict(dim=7, rot=0, n=1000, params=0x1000, o_min=0.005, ws_bytes=need)
+        a.update(b)
+        got = _lib.ubs_relocate(a["dim"], a["rot"], a["n"], a["params"], 0x2000, 0x3000, 0x4000,
+                                a["o_min"], 0x5000, a["ws_bytes"], 0, 0, 0, check=False)
+        assert got == b["code"], b
