@@ -441,7 +441,6 @@ def run_relocate(args, name, desc):
     import numpy as np
     import torch
     from paper_2510_03312_amd.optim import relocate
-    from oracle.preprocess import field_slices  # noqa: F401  (layout only)
     from synth import make_config
 
     cfg = make_config(name)
@@ -450,7 +449,7 @@ def run_relocate(args, name, desc):
     F, n = sc.params.shape
     P = sc.params.copy()
     rng = np.random.default_rng(7)
-    o_row = F - 4
+    o_row = F - 4          # the opacity row: followed only by the three colour rows
     P[o_row] = np.where(rng.uniform(size=n) < 0.3, 0.001, P[o_row]).astype(np.float32)
     base = torch.from_numpy(P).to(dev)
     params = base.clone()
