@@ -66,6 +66,8 @@ WORKLOADS = {
                          "of 1,000,000 7-D primitives (45 rows)"),
     "relocate": ("headline", "relocation of dead primitives (opacity < 0.005, 30% of 1,000,000 "
                              "7-D primitives) to live ones drawn by opacity"),
+    "ssim": ("headline", "image loss (0.8 L1 + 0.2 D-SSIM, 11x11 Gaussian window) and its gradient "
+                         "on one 1920x1080 view"),
 }
 
 
@@ -486,6 +488,46 @@ def run_relocate(args, name, desc):
     }
 
 
+def run_ssim(args, name, desc):
+    """The image loss alone on a 1080p image / target pair."""
+    import numpy as np
+    import torch
+    from paper_2510_03312_amd.optim import ssim_loss
+    from synth import make_config
+
+    cfg = make_config(name)
+    view = cfg["views"][0]
+    A = view.width * view.height
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(3)
+    img = torch.from_numpy(rng.uniform(size=(A, 3)).astype(np.float32)).to(dev)
+    tgt = torch.from_numpy(cfg["targets"][0].reshape(-1, 3).astype(np.float32)).to(dev)
+    for _ in range(args.warmup):
+        ssim_loss(img, tgt, [view])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        ssim_loss(img, tgt, [view])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    # image and target read, gradient written, the per-pixel partials
+    # written once and read once
+    nbytes = A * (24.0 + 12.0 + 72.0)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {
+        "metric": "image loss + gradient evaluations/s (L1 + D-SSIM, 1080p)",
+        "value": round(1000.0 / ms, 2), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": desc, "width": view.width, "height": view.height},
+        "roofline": {"bound": "hbm", "kernel": "ssim", "achieved": round(gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_step": nbytes},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -513,6 +555,8 @@ def main() -> int:
         res = run_adam(args, name, desc)
     elif args.workload == "relocate":
         res = run_relocate(args, name, desc)
+    elif args.workload == "ssim":
+        res = run_ssim(args, name, desc)
     elif name in ("cfg3", "cfg4"):
         res = run_batched(args, name, desc)
     else:

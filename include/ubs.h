@@ -358,6 +358,27 @@ ubs_status ubs_relocate(int32_t dim, int32_t rot, int64_t n, float* params, floa
                         uint64_t* ws_bytes_needed, uint32_t* targets_out, uint64_t* n_dead_out,
                         void* stream);
 
+/*
+ * ubs_ssim_loss -- the image loss of Section 4.5, (1 - lambda_ssim) L1 +
+ * lambda_ssim (1 - SSIM), and its gradient with respect to the image.
+ * SSIM (the measure the paper cites) per pixel and channel under an 11 x 11
+ * Gaussian window, sigma 1.5, zero padding outside each view, C1 = 0.01^2,
+ * C2 = 0.03^2; L1 and SSIM are means over every channel of every pixel of
+ * every view (the paper states neither window nor weight; 0.2 is the usual
+ * lambda_ssim).
+ * sizes: host int32 [n_views][2] (width, height); image, target: device
+ * float32 [sum_v W_v H_v][3], views concatenated, each row-major HWC (the
+ * layout of ubs_render_fwd's image).  d_image: device float32, same shape,
+ * written (feed it to ubs_render_bwd as d_image).  loss: device float64
+ * scalar or NULL.  ws: device workspace of *ws_bytes_needed bytes; ws ==
+ * NULL is a size query.  Asynchronous on stream.  Errors: UBS_ERR_ARG (bad
+ * view size, n_views, lambda outside [0, 1], NULL buffers), UBS_ERR_CAPACITY,
+ * UBS_ERR_UNSUPPORTED (more than 2^31 pixels), UBS_ERR_HIP.
+ */
+ubs_status ubs_ssim_loss(int32_t n_views, const int32_t* sizes, const float* image,
+                         const float* target, float lambda_ssim, float* d_image, double* loss,
+                         void* ws, uint64_t ws_bytes, uint64_t* ws_bytes_needed, void* stream);
+
 /* Number of parameter rows F for a scene (0 for an unsupported dim/rot). */
 int32_t ubs_param_count(int32_t dim, int32_t rot);
 

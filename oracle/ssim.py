@@ -61,7 +61,7 @@ def loss_and_grad(images, targets, lam: float = LAMBDA_SSIM):
     s = sum(ssim_map(x, y).sum() for x, y in zip(Xs, Ys)) / n
     loss = (1.0 - lam) * l1 + lam * (1.0 - s)
     grads = torch.autograd.grad(loss, Xs)
-    return float(loss), [g_.numpy() for g_ in grads]
+    return float(loss.detach()), [g_.numpy() for g_ in grads]
 
 
 def ssim_brute(X: np.ndarray, Y: np.ndarray, i: int, j: int, c: int) -> float:

@@ -10,9 +10,9 @@ from ._lib import (UBS_ROT_QUAT, UBS_ROT_SKEW, UBS_TUNE_NO_BETA_COND,  # noqa: F
 from .renderer import (Renderer, SceneRef, Tuning, UBSRenderFunction, render,  # noqa: F401
                        split_views)
 
-from .optim import AdamConfig, adam_step, relocate  # noqa: F401,E402
+from .optim import AdamConfig, adam_step, relocate, ssim_loss  # noqa: F401,E402
 
-__all__ = ["AdamConfig", "adam_step", "relocate", "Renderer", "SceneRef", "Tuning", "UBSRenderFunction", "render", "split_views",
+__all__ = ["AdamConfig", "adam_step", "relocate", "ssim_loss", "Renderer", "SceneRef", "Tuning", "UBSRenderFunction", "render", "split_views",
            "UBS_ROT_QUAT", "UBS_ROT_SKEW", "UBS_TUNE_PERSISTENT", "UBS_TUNE_PRE_FP32",
            "UBS_TUNE_NO_BETA_COND", "UBS_TUNE_NO_BETA_OPACITY",
            "UbsError", "load"]

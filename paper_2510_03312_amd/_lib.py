@@ -29,7 +29,8 @@ UBS_TUNE_NO_BETA_COND = 4
 UBS_TUNE_NO_BETA_OPACITY = 8
 
 EXPORTS = ("ubs_preprocess", "ubs_bin_sort", "ubs_render_fwd", "ubs_render_bwd",
-           "ubs_adam_step", "ubs_relocate", "ubs_param_count", "ubs_abi_version")
+           "ubs_adam_step", "ubs_relocate", "ubs_ssim_loss", "ubs_param_count",
+           "ubs_abi_version")
 
 
 class UbsScene(ctypes.Structure):
@@ -112,6 +113,10 @@ def load() -> ctypes.CDLL:
                                    c_void_p, c_float, c_void_p, c_uint64, POINTER(c_uint64),
                                    c_void_p, c_void_p, c_void_p]
         L.ubs_relocate.restype = c_int32
+        L.ubs_ssim_loss.argtypes = [c_int32, POINTER(c_int32), c_void_p, c_void_p, c_float,
+                                    c_void_p, c_void_p, c_void_p, c_uint64, POINTER(c_uint64),
+                                    c_void_p]
+        L.ubs_ssim_loss.restype = c_int32
         L.ubs_param_count.argtypes = [c_int32, c_int32]
         L.ubs_param_count.restype = c_int32
         L.ubs_abi_version.argtypes = []
@@ -169,6 +174,19 @@ def ubs_relocate(dim: int, rot: int, n: int, params: int, m: int, v: int, unifor
                                ctypes.byref(need), targets_out, n_dead_out, stream)
     if check:
         _check("ubs_relocate", code)
+    return int(need.value) if not ws else code
+
+
+def ubs_ssim_loss(sizes, image: int, target: int, lambda_ssim: float, d_image: int, loss: int,
+                  ws: int, ws_bytes: int, stream: int, check: bool = True):
+    """sizes: sequence of (width, height).  Returns the workspace bytes needed
+    when ws == 0 (size query), else the code."""
+    arr = (c_int32 * (2 * max(len(sizes), 1)))(*[int(x) for wh in sizes for x in wh])
+    need = c_uint64(0)
+    code = load().ubs_ssim_loss(len(sizes), arr, image, target, lambda_ssim, d_image, loss, ws,
+                                ws_bytes, ctypes.byref(need), stream)
+    if check:
+        _check("ubs_ssim_loss", code)
     return int(need.value) if not ws else code
 
 

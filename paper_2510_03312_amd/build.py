@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libubs.so")
 OBJ = os.path.join(ROOT, "_build", "ubs")
-SOURCES = ["api.hip", "preprocess.hip", "binning.hip", "tile_sort.hip", "raster.hip", "optim.hip", "relocate.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "binning.hip", "tile_sort.hip", "raster.hip", "optim.hip", "relocate.hip", "ssim.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("UBS_OFFLOAD_ARCH", "gfx950")

@@ -1,7 +1,9 @@
-"""Optimiser step (``ubs_adam_step``: the Sec. 4.5 regularisers and spatial
-noise, Adam with the Sec. 5.1 per-group learning rates, in one kernel over a
-scene's [F][n] parameters) and the relocation of dead primitives
-(``ubs_relocate``: Sec. 4.5 cloning rule).  Argument marshalling only."""
+"""Training-step pieces around the renderer: the image loss with D-SSIM
+(``ubs_ssim_loss``), the optimiser step (``ubs_adam_step``: the Sec. 4.5
+regularisers and spatial noise, Adam with the Sec. 5.1 per-group learning
+rates, in one kernel over a scene's [F][n] parameters) and the relocation
+of dead primitives (``ubs_relocate``: Sec. 4.5 cloning rule).  Argument
+marshalling only."""
 from __future__ import annotations
 
 from dataclasses import dataclass
@@ -78,3 +80,21 @@ def relocate(params: torch.Tensor, m: torch.Tensor, v: torch.Tensor, uniforms: t
                       uniforms.data_ptr(), o_min, ws.data_ptr(), ws.numel(), targets.data_ptr(),
                       n_dead.data_ptr(), stream)
     return targets, n_dead
+
+
+def ssim_loss(image: torch.Tensor, target: torch.Tensor, views, lambda_ssim: float = 0.2):
+    """(1 - lambda) L1 + lambda (1 - SSIM) over the views of a frame (image,
+    target: float32 [sum H W, 3] as the renderer produces).  Returns (loss,
+    d_image): a float64 device scalar and the image gradient."""
+    sizes = [(v.width, v.height) for v in views]
+    A = sum(w * h for w, h in sizes)
+    for name, t in (("image", image), ("target", target)):
+        _check_tensor(name, t, (A, 3))
+    need = _lib.ubs_ssim_loss(sizes, 0, 0, lambda_ssim, 0, 0, 0, 0, 0)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=image.device)
+    d_image = torch.empty_like(image)
+    loss = torch.zeros(1, dtype=torch.float64, device=image.device)
+    _lib.ubs_ssim_loss(sizes, image.data_ptr(), target.data_ptr(), lambda_ssim,
+                       d_image.data_ptr(), loss.data_ptr(), ws.data_ptr(), ws.numel(),
+                       torch.cuda.current_stream().cuda_stream)
+    return loss, d_image

@@ -208,3 +208,16 @@ def test_relocate_size_query_and_errors():
         got = _lib.ubs_relocate(a["dim"], a["rot"], a["n"], a["params"], 0x2000, 0x3000, 0x4000,
                                 a["o_min"], 0x5000, a["ws_bytes"], 0, 0, 0, check=False)
         assert got == b["code"], b
+
+
+def test_ssim_loss_size_query_and_errors():
+    need = _lib.ubs_ssim_loss([(64, 48), (30, 20)], 0, 0, 0.2, 0, 0, 0, 0, 0)
+    assert need >= (64 * 48 + 30 * 20) * 36
+    cases = [(dict(sizes=[(0, 5)]), _lib.UBS_ERR_ARG), (dict(lam=1.5), _lib.UBS_ERR_ARG),
+             (dict(ws_bytes=8), _lib.UBS_ERR_CAPACITY), (dict(image=0), _lib.UBS_ERR_ARG)]
+    for change, code in cases:
+        a = dict(sizes=[(64, 48)], lam=0.2, image=0x1000, ws_bytes=need)
+        a.update(change)
+        got = _lib.ubs_ssim_loss(a["sizes"], a["image"], 0x2000, a["lam"], 0x3000, 0, 0x4000,
+                                 a["ws_bytes"], 0, check=False)
+        assert got == code, change
