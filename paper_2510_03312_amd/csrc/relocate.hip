@@ -13,7 +13,8 @@
 //             slots in index order
 //   sample    slot k: first j with cdf[j] > u_k * total (float64), one
 //             atomic per slot on the copy count of j
-//   apply     slot k copies column j, both get o'; their Adam moments reset
+//   apply     row by row: a dead primitive takes its pick's row (or o'), a
+//             picked one gets o', the moments of both are zeroed
 #include <cmath>
 
 #include "ubs_internal.hpp"
@@ -158,13 +159,14 @@ __device__ __forceinline__ int64_t first_index(const double* __restrict__ cdf, i
 __global__ void __launch_bounds__(kRelThreads) reloc_sample_kernel(
     const double* __restrict__ cdf, int64_t n, const unsigned long long* __restrict__ n_dead,
     const double* __restrict__ uniforms, uint32_t* __restrict__ targets,
-    uint32_t* __restrict__ counts) {
+    uint32_t* __restrict__ counts, uint32_t* __restrict__ targets_out) {
   const int64_t k = int64_t(blockIdx.x) * kRelThreads + threadIdx.x;
   const double total = cdf[n - 1];
   if (k >= int64_t(*n_dead) || !(total > 0.0)) return;
   int64_t j = first_index<true>(cdf, n, uniforms[k] * total);
   if (j >= n) j = first_index<false>(cdf, n, total);
   targets[k] = uint32_t(j);
+  if (targets_out) targets_out[k] = uint32_t(j);
   atomicAdd(&counts[j], 1u);
 }
 
@@ -173,28 +175,36 @@ __global__ void copy_count_kernel(const unsigned long long* __restrict__ src,
   if (threadIdx.x == 0) *dst = *src;
 }
 
+// One (row, primitive) pair per thread, rows along blockIdx.y, so that the
+// accesses of a wavefront to one row are consecutive: a dead primitive i
+// takes row r of its pick j = targets[offs[i]] (or the cloned opacity), a
+// picked primitive gets the cloned opacity, and both have their moments
+// zeroed.  Picks are never dead, so no thread reads what another writes.
 __global__ void __launch_bounds__(kRelThreads) reloc_apply_kernel(
-    float* __restrict__ params, float* __restrict__ m, float* __restrict__ v, int64_t n, int F,
+    float* __restrict__ params, float* __restrict__ m, float* __restrict__ v, int64_t n,
     int o_row, const double* __restrict__ cdf, const float* __restrict__ o_keep,
-    const uint32_t* __restrict__ list, const unsigned long long* __restrict__ n_dead,
-    const uint32_t* __restrict__ targets, const uint32_t* __restrict__ counts,
-    uint32_t* __restrict__ targets_out) {
-  const int64_t k = int64_t(blockIdx.x) * kRelThreads + threadIdx.x;
-  if (k >= int64_t(*n_dead) || !(cdf[n - 1] > 0.0)) return;
-  const int64_t d = list[k];
-  const int64_t j = targets[k];
-  const double copies = double(counts[j]) + 1.0;
-  const float o_new = float(1.0 - pow(1.0 - double(o_keep[j]), 1.0 / copies));
-  for (int r = 0; r < F; ++r) {
-    const int64_t row = int64_t(r) * n;
-    params[row + d] = r == o_row ? o_new : params[row + j];
-    m[row + d] = 0.0f;
-    v[row + d] = 0.0f;
-    m[row + j] = 0.0f;   // every copy of j writes the same zeros and o'
-    v[row + j] = 0.0f;
+    const uint32_t* __restrict__ dead, const uint32_t* __restrict__ offs,
+    const uint32_t* __restrict__ targets, const uint32_t* __restrict__ counts) {
+  const int64_t i = int64_t(blockIdx.x) * kRelThreads + threadIdx.x;
+  if (i >= n || !(cdf[n - 1] > 0.0)) return;
+  const int r = blockIdx.y;
+  const int64_t row = int64_t(r) * n;
+  if (dead[i]) {
+    const int64_t j = targets[offs[i]];
+    float val;
+    if (r == o_row)
+      val = float(1.0 - pow(1.0 - double(o_keep[j]), 1.0 / (double(counts[j]) + 1.0)));
+    else
+      val = params[row + j];
+    params[row + i] = val;
+    m[row + i] = 0.0f;
+    v[row + i] = 0.0f;
+  } else if (counts[i] > 0u) {
+    if (r == o_row)
+      params[row + i] = float(1.0 - pow(1.0 - double(o_keep[i]), 1.0 / (double(counts[i]) + 1.0)));
+    m[row + i] = 0.0f;
+    v[row + i] = 0.0f;
   }
-  params[int64_t(o_row) * n + j] = o_new;
-  if (targets_out) targets_out[k] = uint32_t(j);
 }
 
 }  // namespace ubs
@@ -242,9 +252,9 @@ extern "C" ubs_status ubs_relocate(int32_t dim, int32_t rot, int64_t n, float* p
     return UBS_ERR_HIP;
   if (launch_compact(dead, offs, uint32_t(n), list, st) != hipSuccess) return UBS_ERR_HIP;
   hipLaunchKernelGGL(reloc_sample_kernel, dim3(blocks), dim3(kRelThreads), 0, st, cdf, n, n_dead,
-                     uniforms, targets, counts);
-  hipLaunchKernelGGL(reloc_apply_kernel, dim3(blocks), dim3(kRelThreads), 0, st, params, m, v, n,
-                     pr.F, pr.o, cdf, o_keep, list, n_dead, targets, counts, targets_out);
+                     uniforms, targets, counts, targets_out);
+  hipLaunchKernelGGL(reloc_apply_kernel, dim3(blocks, unsigned(pr.F)), dim3(kRelThreads), 0, st,
+                     params, m, v, n, pr.o, cdf, o_keep, dead, offs, targets, counts);
   if (n_dead_out)
     hipLaunchKernelGGL(copy_count_kernel, dim3(1), dim3(64), 0, st, n_dead, n_dead_out);
   return hipGetLastError() == hipSuccess ? UBS_OK : UBS_ERR_HIP;
