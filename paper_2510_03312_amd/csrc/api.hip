@@ -19,8 +19,9 @@ hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const 
                                  int n_views, const float* records, const float* grad2d,
                                  const uint32_t* live, const uint32_t* offs, const uint32_t* list,
                                  const unsigned long long* n_live, float* compact, hipStream_t st);
-hipError_t launch_compact(const uint32_t* flags, const uint32_t* offsets, uint32_t n,
-                          uint32_t* list, hipStream_t st);
+hipError_t launch_scan_compact(const uint32_t* flags, uint32_t n, uint32_t* tile_sums,
+                               uint32_t* offsets, uint32_t* list, hipStream_t st,
+                               unsigned long long* total_out);
 hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
                             uint32_t n_records, uint32_t* tile_counts, uint32_t* hit_mask,
                             uint32_t* big_list, uint32_t* big_count, hipStream_t st);
@@ -442,9 +443,8 @@ ubs_status ubs_render_bwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
     uint32_t* list = at<uint32_t>(ws, L.off_live_list) + p.ds[sc].prim_base;
     unsigned long long* n_live = at<unsigned long long>(ws, L.off_live_count) + sc;
     uint32_t* offs = at<uint32_t>(ws, L.off_offsets);
-    UBS_HIP(launch_scan(live, uint32_t(p.ds[sc].n), at<uint32_t>(ws, L.off_blocksums), offs,
-                        nullptr, 0ull, s, n_live));
-    UBS_HIP(launch_compact(live, offs, uint32_t(p.ds[sc].n), list, s));
+    UBS_HIP(launch_scan_compact(live, uint32_t(p.ds[sc].n), at<uint32_t>(ws, L.off_blocksums),
+                                offs, list, s, n_live));
     UBS_HIP(launch_preprocess_bwd(fp64, p.ds[sc], sc, views, frame->n_views,
                                   at<float>(ws, L.pub.off_records), grad2d, live, offs, list,
                                   n_live, at<float>(ws, L.off_grad_compact), s));

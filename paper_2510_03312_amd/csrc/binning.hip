@@ -430,9 +430,11 @@ __global__ void __launch_bounds__(kScanThreads) scan_tile_sums_scan_kernel(
   if (threadIdx.x == 0 && total_out != nullptr) *total_out = carry;
 }
 
+// With `list` (0/1 inputs only), also the compaction: list[out[i]] = i for
+// every set in[i].
 __global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(
     const uint32_t* __restrict__ in, uint32_t n, const uint32_t* __restrict__ tile_sums,
-    uint32_t* __restrict__ out) {
+    uint32_t* __restrict__ out, uint32_t* __restrict__ list) {
   __shared__ uint32_t lds[8];
   const size_t base = size_t(blockIdx.x) * kScanTile + size_t(threadIdx.x) * kScanItems;
   uint32_t vals[kScanItems];
@@ -446,7 +448,10 @@ __global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(
   uint32_t run = block_exclusive_scan_u32(s, lds, &tot) + tile_sums[blockIdx.x];
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < n) out[base + k] = run;
+    if (base + k < n) {
+      out[base + k] = run;
+      if (list != nullptr && vals[k] != 0u) list[run] = uint32_t(base + k);
+    }
     run += vals[k];
   }
 }
@@ -486,7 +491,7 @@ constexpr uint32_t kSingleScanMax = 16u * kScanTile;
 
 __global__ void __launch_bounds__(kScanThreads) scan_single_kernel(
     const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ out,
-    DevStatus* __restrict__ status, unsigned long long capacity,
+    uint32_t* __restrict__ list, DevStatus* __restrict__ status, unsigned long long capacity,
     unsigned long long* __restrict__ total_out) {
   __shared__ uint32_t lds[8];
   __shared__ unsigned long long lds4[4];
@@ -508,7 +513,10 @@ __global__ void __launch_bounds__(kScanThreads) scan_single_kernel(
     total += block_sum_u64(s64, lds4);
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-      if (base + k < n) out[base + k] = run;
+      if (base + k < n) {
+        out[base + k] = run;
+        if (list != nullptr && vals[k] != 0u) list[run] = base + k;
+      }
       run += vals[k];
     }
     carry += tot32;
@@ -520,12 +528,12 @@ __global__ void __launch_bounds__(kScanThreads) scan_single_kernel(
   if (threadIdx.x == 0 && total_out != nullptr) *total_out = total;
 }
 
-hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
-                       DevStatus* status, unsigned long long capacity, hipStream_t st,
-                       unsigned long long* total_out) {
+static hipError_t scan_impl(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
+                            uint32_t* list, DevStatus* status, unsigned long long capacity,
+                            hipStream_t st, unsigned long long* total_out) {
   if (n <= kSingleScanMax) {
-    hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kScanThreads), 0, st, in, n, out, status,
-                       capacity, total_out);
+    hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kScanThreads), 0, st, in, n, out, list,
+                       status, capacity, total_out);
     return hipGetLastError();
   }
   const uint32_t n_tiles = (n + kScanTile - 1) / kScanTile;
@@ -536,8 +544,22 @@ hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint
                      n_tiles, status, capacity, total_out);
   if (n_tiles > 0)
     hipLaunchKernelGGL(scan_apply_kernel, dim3(n_tiles), dim3(kScanThreads), 0, st, in, n,
-                       tile_sums, out);
+                       tile_sums, out, list);
   return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
+                       DevStatus* status, unsigned long long capacity, hipStream_t st,
+                       unsigned long long* total_out) {
+  return scan_impl(in, n, tile_sums, out, nullptr, status, capacity, st, total_out);
+}
+
+// Exclusive scan of a 0/1 flag array and, in the same pass, the compacted
+// list of its set entries (ascending); *total_out gets their number.
+hipError_t launch_scan_compact(const uint32_t* flags, uint32_t n, uint32_t* tile_sums,
+                               uint32_t* offsets, uint32_t* list, hipStream_t st,
+                               unsigned long long* total_out) {
+  return scan_impl(flags, n, tile_sums, offsets, list, nullptr, 0ull, st, total_out);
 }
 
 hipError_t launch_bin_emit(const float* records, const DevView* views, int n_views,
@@ -552,20 +574,6 @@ hipError_t launch_bin_emit(const float* records, const DevView* views, int n_vie
   return hipGetLastError();
 }
 
-// Compacted list of the set entries of a 0/1 flag array, given its exclusive scan.
-__global__ void __launch_bounds__(256) compact_kernel(const uint32_t* __restrict__ flags,
-                                                      const uint32_t* __restrict__ offsets,
-                                                      uint32_t n, uint32_t* __restrict__ list) {
-  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-  if (i < n && flags[i]) list[offsets[i]] = i;
-}
-
-hipError_t launch_compact(const uint32_t* flags, const uint32_t* offsets, uint32_t n,
-                          uint32_t* list, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(compact_kernel, dim3((n + 255) / 256), dim3(256), 0, st, flags, offsets, n, list);
-  return hipGetLastError();
-}
 
 // First kernel of the binning: zeroes the n_words counters at `words`, and
 // workgroup 0 adds up the per-workgroup counts preprocess left (visible

@@ -23,21 +23,18 @@ namespace ubs {
 template <typename T> __device__ __forceinline__ T m_exp(T x);
 template <> __device__ __forceinline__ float m_exp<float>(float x) { return expf(x); }
 template <> __device__ __forceinline__ double m_exp<double>(double x) { return exp(x); }
-template <typename T> __device__ __forceinline__ T m_log(T x);
-template <> __device__ __forceinline__ float m_log<float>(float x) { return logf(x); }
-template <> __device__ __forceinline__ double m_log<double>(double x) { return log(x); }
-template <typename T> __device__ __forceinline__ T m_log1p(T x);
-template <> __device__ __forceinline__ float m_log1p<float>(float x) { return log1pf(x); }
-template <> __device__ __forceinline__ double m_log1p<double>(double x) { return log1p(x); }
 template <typename T> __device__ __forceinline__ T m_sqrt(T x);
 template <> __device__ __forceinline__ float m_sqrt<float>(float x) { return sqrtf(x); }
 template <> __device__ __forceinline__ double m_sqrt<double>(double x) { return sqrt(x); }
-template <typename T> __device__ __forceinline__ T m_tanh(T x);
-template <> __device__ __forceinline__ float m_tanh<float>(float x) { return tanhf(x); }
-template <> __device__ __forceinline__ double m_tanh<double>(double x) { return tanh(x); }
-template <typename T> __device__ __forceinline__ T m_pow(T x, T y);
-template <> __device__ __forceinline__ float m_pow<float>(float x, float y) { return powf(x, y); }
-template <> __device__ __forceinline__ double m_pow<double>(double x, double y) { return pow(x, y); }
+
+// Scalar factors of the opacity (the modulation terms, o(q), beta_x, rho)
+// are well conditioned in their arguments, so they are evaluated in float32
+// whatever T is; the linear algebra of the conditioning stays in T.
+__device__ __forceinline__ float s_exp(float x) { return expf(x); }
+__device__ __forceinline__ float s_log1p_exp_m2(float x) { return log1pf(expf(-2.0f * x)); }
+// 1 - y^(-1/beta) for y >= 1, as -expm1(-log(y) / beta) (no cancellation for
+// y near 1)
+__device__ __forceinline__ float s_rho(float y, float beta) { return -expm1f(-logf(y) / beta); }
 
 template <int C> struct Cdim { static constexpr int V = C > 0 ? C : 1; };
 
@@ -285,11 +282,11 @@ __device__ __forceinline__ void view_forward(const Raw<C, ROT>& r, const Geo<T, 
       T x = acc * acc;
       // Gaussian opacity (ablation): e = 1 and ell = -w^2 / 2
       s.ell[i] = g.beta_opacity
-                     ? T(0.69314718055994530942) - T(2) * x - m_log1p<T>(m_exp<T>(T(-2) * x))
+                     ? T(0.69314718055994530942) - T(2) * x - T(s_log1p_exp_m2(float(x)))
                      : T(-0.5) * x;
       lsum += g.e[i] * s.ell[i];
     }
-    oq = T(r.o) * m_exp<T>(lsum);
+    oq = T(r.o) * T(s_exp(float(lsum)));
     // conditioning: K = Sigma_xq Sigma_q^-1 = (Sigma_xq Lh^-T) Lh^-1
     T K[3][Cdim<C>::V];
 #pragma unroll
@@ -377,10 +374,10 @@ __device__ __forceinline__ void view_forward(const Raw<C, ROT>& r, const Geo<T, 
   s.ca = s.Sp11 * idet;
   s.cb = -s.Sp01 * idet;
   s.cc = s.Sp00 * idet;
-  s.beta = T(4) * m_exp<T>(T(r.bx));
+  s.beta = T(4) * T(s_exp(r.bx));
   if (!(oq >= T(kAlphaMin))) live = false;
   T oqs = oq >= T(kAlphaMin) ? oq : T(1);
-  s.rho = T(1) - m_pow<T>(T(255) * oqs, T(-1) / s.beta);
+  s.rho = T(s_rho(float(T(255) * oqs), float(s.beta)));
   if (!(s.rho > T(0))) live = false;
   s.live = live;
 }
@@ -553,12 +550,12 @@ __device__ __forceinline__ void view_backward(const Raw<C, ROT>& r, const Geo<T,
       gv[k] = g.bt[k] * Zu[k];
     }
     // ---- opacity ----  o(q) = o exp(sum e_i ell_i),  ell = log(1 - tanh(w^2))
-    T prod = m_exp<T>(T(0));
+    T prod;
     {
       T lsum = T(0);
 #pragma unroll
       for (int i = 0; i < C; ++i) lsum += g.e[i] * s.ell[i];
-      prod = m_exp<T>(lsum);
+      prod = T(s_exp(float(lsum)));
     }
     G.o += goq * prod;
     T gw[Cdim<C>::V];
@@ -567,7 +564,7 @@ __device__ __forceinline__ void view_backward(const Raw<C, ROT>& r, const Geo<T,
       if (g.beta_opacity) {
         G.bq[i] += goq * s.oq * s.ell[i] * g.e[i];
         T x = s.w[i] * s.w[i];
-        T th = m_tanh<T>(x);
+        T th = T(tanhf(float(x)));
         gw[i] = goq * s.oq * g.e[i] * (-(T(1) + th)) * T(2) * s.w[i];
       } else {
         gw[i] = -goq * s.oq * s.w[i];   // d(-w^2/2)/dw; no b_q dependence

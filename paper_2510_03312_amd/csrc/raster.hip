@@ -11,10 +11,10 @@
 // transmittance below 1e-4; the wavefront stops when all its pixels have.
 // Backward: each tile is walked back to front from the last contributor;
 // the transmittance in front of a record is recovered by division.  A lane
-// first sums the gradient terms of its own pixels, the wavefront then sums
-// over each 16-lane row with a DPP scan, passes the four row totals through
-// LDS, and lanes 0..9 add the ten per-record totals to the record's
-// accumulator with one atomic each.
+// first sums the gradient terms of its own pixels; the wavefront then folds
+// its ten per-record sums onto fewer lanes with lane swaps, finishes them
+// with DPP sums within 16-lane rows, and four lanes add the ten totals to
+// the record's accumulator with one atomic each.
 //
 // Both passes take every per-pixel decision (support test, skip, stop)
 // through the same inline functions, so the backward pass visits exactly
@@ -185,22 +185,23 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(
                                    image, t_ws, t_user, ncontrib);
 }
 
-// Inclusive sums over each 16-lane row by DPP row_shr scans, of N values at
-// once: lane 15 of a row (lanes 15, 31, 47, 63) ends with the row's totals.
+// Sums over each 16-lane row by DPP row rotations (by 1, 2, 4, 8), of N
+// values at once: every lane of a row ends with the row's totals.  A rotation
+// has no out-of-row source lane, so each step is one DPP add.
 template <int CTRL>
-__device__ __forceinline__ float dpp_shr(float x) {
+__device__ __forceinline__ float dpp_row(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
 template <int N>
-__device__ __forceinline__ void row_scan_all(float* v) {
+__device__ __forceinline__ void row_sum_all(float* v) {
 #pragma unroll
-  for (int q = 0; q < N; ++q) v[q] += dpp_shr<0x111>(v[q]);
+  for (int q = 0; q < N; ++q) v[q] += dpp_row<0x121>(v[q]);
 #pragma unroll
-  for (int q = 0; q < N; ++q) v[q] += dpp_shr<0x112>(v[q]);
+  for (int q = 0; q < N; ++q) v[q] += dpp_row<0x122>(v[q]);
 #pragma unroll
-  for (int q = 0; q < N; ++q) v[q] += dpp_shr<0x114>(v[q]);
+  for (int q = 0; q < N; ++q) v[q] += dpp_row<0x124>(v[q]);
 #pragma unroll
-  for (int q = 0; q < N; ++q) v[q] += dpp_shr<0x118>(v[q]);
+  for (int q = 0; q < N; ++q) v[q] += dpp_row<0x128>(v[q]);
 }
 // Lane exchanges of gfx950: swap_halves(a, b) returns (a with its upper 32
 // lanes replaced by b's lower 32, b with its lower 32 replaced by a's upper
@@ -217,10 +218,12 @@ __device__ __forceinline__ FPair swap_rows(float a, float b) {
   const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
   return FPair{__uint_as_float(r[0]), __uint_as_float(r[1])};
 }
-__device__ __forceinline__ float opaque_zero() {
-  float z;
-  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
-  return z;
+// Two zeros from one 64-bit move, which the compiler cannot rematerialise.
+__device__ __forceinline__ void opaque_zero2(float& a, float& b) {
+  uint64_t z;
+  asm volatile("v_mov_b64 %0, 0" : "=v"(z));
+  a = __uint_as_float(uint32_t(z));
+  b = __uint_as_float(uint32_t(z >> 32));
 }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -304,8 +307,11 @@ __device__ __forceinline__ void raster_bwd_tile(
       // per-lane sums over the lane's pixels
       // (zeros the compiler cannot rematerialise: otherwise it re-creates
       // them on every path that skips the first pixel's update)
-      float a_r = opaque_zero(), a_g = opaque_zero(), a_b = opaque_zero(), a_o = opaque_zero();
-      float a_be = opaque_zero(), a_dr = opaque_zero(), a_dry = opaque_zero(), a_dryy = opaque_zero();
+      float a_r, a_g, a_b, a_o, a_be, a_dr, a_dry, a_dryy;
+      opaque_zero2(a_r, a_g);
+      opaque_zero2(a_b, a_o);
+      opaque_zero2(a_be, a_dr);
+      opaque_zero2(a_dry, a_dryy);
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
@@ -356,8 +362,8 @@ __device__ __forceinline__ void raster_bwd_tile(
       gv[5] = a_o * inv_o;
       // sums over the wavefront: halves folded onto each other (permlane32
       // swap: field 2p in lanes 0-31, 2p+1 in lanes 32-63), row pairs folded
-      // (permlane16 swap: one field per row), DPP scans within the rows;
-      // lane 15 of each row ends with the totals of its rows' fields
+      // (permlane16 swap: one field per row), DPP sums within the rows;
+      // every lane of a row ends with the totals of its row's fields
       float h[5];
 #pragma unroll
       for (int p = 0; p < 5; ++p) {
@@ -373,14 +379,18 @@ __device__ __forceinline__ void raster_bwd_tile(
         t3[1] = s1.a + s1.b;
         t3[2] = s2.a + s2.b;
       }
-      row_scan_all<3>(t3);
+      row_sum_all<3>(t3);
+      // keep the last DPP add ahead of the branch (sunk into it, the add
+      // could no longer take its operand through DPP)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) asm volatile("" : "+v"(t3[q]));
       if ((lane & 15) == 15) {
         const int row = lane >> 4;
         const int sub = row == 1 ? 2 : (row == 2 ? 1 : row);
         float* g = grad2d + size_t(__float_as_uint(g2.w)) * kGradFloats;
-        if (t3[0] != 0.0f) atomicAdd(g + sub, t3[0]);
-        if (t3[1] != 0.0f) atomicAdd(g + 4 + sub, t3[1]);
-        if ((row & 1) == 0 && t3[2] != 0.0f) atomicAdd(g + 8 + (row >> 1), t3[2]);
+        atomicAdd(g + sub, t3[0]);
+        atomicAdd(g + 4 + sub, t3[1]);
+        if ((row & 1) == 0) atomicAdd(g + 8 + (row >> 1), t3[2]);
       }
     }
     hi = lo;

@@ -21,11 +21,9 @@
 
 namespace ubs {
 
-hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
-                       DevStatus* status, unsigned long long capacity, hipStream_t st,
-                       unsigned long long* total_out);
-hipError_t launch_compact(const uint32_t* flags, const uint32_t* offsets, uint32_t n,
-                          uint32_t* list, hipStream_t st);
+hipError_t launch_scan_compact(const uint32_t* flags, uint32_t n, uint32_t* tile_sums,
+                               uint32_t* offsets, uint32_t* list, hipStream_t st,
+                               unsigned long long* total_out);
 
 constexpr int kRelThreads = 256;
 constexpr int kRelItems = 16;
@@ -247,10 +245,9 @@ extern "C" ubs_status ubs_relocate(int32_t dim, int32_t rot, int64_t n, float* p
   hipLaunchKernelGGL(cdf_tile_sums_kernel, dim3(L.n_tiles), dim3(kRelThreads), 0, st, cdf, n, sums);
   hipLaunchKernelGGL(cdf_sums_scan_kernel, dim3(1), dim3(kRelThreads), 0, st, sums, L.n_tiles);
   hipLaunchKernelGGL(cdf_apply_kernel, dim3(L.n_tiles), dim3(kRelThreads), 0, st, cdf, n, sums);
-  if (launch_scan(dead, uint32_t(n), reinterpret_cast<uint32_t*>(base + L.sums_u32), offs,
-                  nullptr, 0ull, st, n_dead) != hipSuccess)
+  if (launch_scan_compact(dead, uint32_t(n), reinterpret_cast<uint32_t*>(base + L.sums_u32), offs,
+                          list, st, n_dead) != hipSuccess)
     return UBS_ERR_HIP;
-  if (launch_compact(dead, offs, uint32_t(n), list, st) != hipSuccess) return UBS_ERR_HIP;
   hipLaunchKernelGGL(reloc_sample_kernel, dim3(blocks), dim3(kRelThreads), 0, st, cdf, n, n_dead,
                      uniforms, targets, counts, targets_out);
   hipLaunchKernelGGL(reloc_apply_kernel, dim3(blocks, unsigned(pr.F)), dim3(kRelThreads), 0, st,
