@@ -50,7 +50,7 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 #   pair     per (tile, record): dx and the column terms of the tile's 16
 #            pixel columns (4 each), 1/o, the ten sums turned into the
 #            record-field gradients (14)                                  64 + 4 + 14
-BWD_OPS = {"eval": 4, "support": 12, "contrib": 27, "grad": 15, "pair": 82}
+BWD_OPS = {"eval": 4, "support": 12, "contrib": 20, "grad": 13, "pair": 82}
 
 WORKLOADS = {
     "headline": ("headline", "1,000,000 7-D Beta primitives (quaternion rotation), one "

@@ -233,7 +233,8 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
   return x;
 }
 
-template <int TW, int TH, int BATCH>
+// HAS_DT: a gradient of the final transmittance is given (d_tfinal).
+template <int TW, int TH, int BATCH, bool HAS_DT>
 __device__ __forceinline__ void raster_bwd_tile(
     uint32_t tile, float4* s0, float4* s1, float4* s2,
     const float* __restrict__ records,
@@ -253,22 +254,25 @@ __device__ __forceinline__ void raster_bwd_tile(
   const int py0 = ty * TH + lane / TW;
   const float fx = float(px) + 0.5f;
   const uint32_t start = ranges[2 * size_t(tile)];
-  float Tf[PPL], T[PPL], Sr[PPL], Sg[PPL], Sb[PPL], gR[PPL], gG[PPL], gB[PPL], gT[PPL];
+  // gTf: d loss / d T_final times T_final (the transmittance gradient enters
+  // every record's d alpha as - gTf / (1 - alpha))
+  float T[PPL], Sr[PPL], Sg[PPL], Sb[PPL], gR[PPL], gG[PPL], gB[PPL], gTf[PPL];
   uint32_t last[PPL];
   uint32_t lane_max = 0;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int py = py0 + k * RSTEP;
-    Tf[k] = 1.0f; gR[k] = gG[k] = gB[k] = gT[k] = 0.0f; last[k] = 0;
+    float Tf = 1.0f;
+    gR[k] = gG[k] = gB[k] = gTf[k] = 0.0f; last[k] = 0;
     if (px < V.W && py < V.H) {
       const size_t pix = size_t(V.pix_base) + size_t(py) * V.W + px;
-      Tf[k] = t_ws[pix];
+      Tf = t_ws[pix];
       last[k] = ncontrib[pix];
       if (d_image) {
         gR[k] = d_image[3 * pix];
         gG[k] = d_image[3 * pix + 1];
         gB[k] = d_image[3 * pix + 2];
-        if (d_tfinal) gT[k] = d_tfinal[pix];
+        if (HAS_DT) gTf[k] = d_tfinal[pix] * Tf;
       } else {
         const float e0 = l1_image[3 * pix] - l1_target[3 * pix];
         const float e1 = l1_image[3 * pix + 1] - l1_target[3 * pix + 1];
@@ -278,7 +282,7 @@ __device__ __forceinline__ void raster_bwd_tile(
         gB[k] = e2 > 0.0f ? l1_scale : (e2 < 0.0f ? -l1_scale : 0.0f);
       }
     }
-    T[k] = Tf[k];
+    T[k] = Tf;
     Sr[k] = Sg[k] = Sb[k] = 0.0f;
     lane_max = max(lane_max, last[k]);
   }
@@ -303,8 +307,12 @@ __device__ __forceinline__ void raster_bwd_tile(
       const float4 g0 = s0[j], g1 = s1[j], g2 = s2[j];
       const float dx = fx - g0.x;
       const ColTerms ct = col_terms(g0, dx);
-      const float inv_o = hw_exp2(-g1.z);   // 1 / o: d sigma / d o = sigma / o
-      // per-lane sums over the lane's pixels
+      // per-lane sums over the lane's pixels, with the factors common to a
+      // record (1/o, ln 2, -beta) applied after the sums:
+      //   a_o = sum s,  a_be = sum s log2(1 - r),  a_dr = sum s / (1 - r)
+      //   (a_dry, a_dryy: times dy, dy^2) with s = sigma d loss / d alpha;
+      //   d sigma / d o = sigma / o, d sigma / d beta = sigma ln(1 - r),
+      //   d sigma / d r = -beta sigma / (1 - r)
       // (zeros the compiler cannot rematerialise: otherwise it re-creates
       // them on every path that skips the first pixel's update)
       float a_r, a_g, a_b, a_o, a_be, a_dr, a_dry, a_dryy;
@@ -324,42 +332,49 @@ __device__ __forceinline__ void raster_bwd_tile(
         const float alpha = fminf(kAlphaMax, sigma);
         if (alpha < kAlphaMin) continue;
         any = true;
-        const float oma = 1.0f - alpha;
-        const float ioma = fast_rcp(oma);
+        const float ioma = fast_rcp(1.0f - alpha);
         const float Ti = T[k] * ioma;
         const float w = alpha * Ti;
         a_r += gR[k] * w;
         a_g += gG[k] * w;
         a_b += gB[k] * w;
-        const float dalpha = Ti * (gR[k] * (g2.x - Sr[k]) + gG[k] * (g2.y - Sg[k]) +
-                                   gB[k] * (g2.z - Sb[k])) - gT[k] * Tf[k] * ioma;
-        Sr[k] = alpha * g2.x + oma * Sr[k];
-        Sg[k] = alpha * g2.y + oma * Sg[k];
-        Sb[k] = alpha * g2.z + oma * Sb[k];
-        T[k] = Ti;
+        // colour in front of the record minus the colour behind it; the
+        // colour behind updates as S += alpha (c - S)
+        const float er = g2.x - Sr[k], eg = g2.y - Sg[k], eb = g2.z - Sb[k];
         if (sigma < kAlphaMax) {
-          a_o += dalpha * sigma;                            // times 1/o after the sums
-          a_be += dalpha * sigma * l2 * 0.69314718f;        // d sigma / d beta
-          const float dr = -dalpha * g1.w * sigma * fast_rcp(1.0f - r);  // d sigma / d r
-          a_dr += dr;
-          a_dry += dr * dy;
-          a_dryy += dr * dy * dy;
+          const float dot = gR[k] * er + gG[k] * eg + gB[k] * eb;
+          const float dalpha = HAS_DT ? Ti * dot - gTf[k] * ioma : Ti * dot;
+          const float sd = sigma * dalpha;
+          a_o += sd;
+          a_be += sd * l2;
+          const float q = sd * fast_rcp(1.0f - r);
+          a_dr += q;
+          const float qy = q * dy;
+          a_dry += qy;
+          a_dryy += qy * dy;
         }
+        Sr[k] += alpha * er;
+        Sg[k] += alpha * eg;
+        Sb[k] += alpha * eb;
+        T[k] = Ti;
       }
       if (__ballot(any) == 0ull) continue;
-      // record-field gradients of this lane: r = a dx^2 + 2 b dx dy + c dy^2
+      // record-field gradients of this lane: r = a dx^2 + 2 b dx dy + c dy^2,
+      // d r sums = -beta (a_dr, a_dry, a_dryy)
       const float b = 0.5f * g0.w;
+      const float nb = -g1.w, nb2 = -2.0f * g1.w;
+      const float A = nb * a_dr, D = nb * a_dry;
       float gv[kGradFloats];
-      gv[0] = -2.0f * (g0.z * dx * a_dr + b * a_dry);
-      gv[1] = -2.0f * (b * dx * a_dr + g1.x * a_dry);
-      gv[2] = dx * dx * a_dr;
-      gv[3] = 2.0f * dx * a_dry;
-      gv[4] = a_dryy;
-      gv[6] = a_be;
+      gv[0] = -2.0f * (g0.z * dx * A + b * D);
+      gv[1] = -2.0f * (b * dx * A + g1.x * D);
+      gv[2] = dx * dx * A;
+      gv[3] = nb2 * dx * a_dry;
+      gv[4] = nb * a_dryy;
+      gv[6] = a_be * 0.69314718f;
       gv[7] = a_r;
       gv[8] = a_g;
       gv[9] = a_b;
-      gv[5] = a_o * inv_o;
+      gv[5] = a_o * hw_exp2(-g1.z);   // times 1 / o
       // sums over the wavefront: halves folded onto each other (permlane32
       // swap: field 2p in lanes 0-31, 2p+1 in lanes 32-63), row pairs folded
       // (permlane16 swap: one field per row), DPP sums within the rows;
@@ -406,10 +421,16 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(
     const float* __restrict__ d_tfinal, const float* __restrict__ l1_image,
     const float* __restrict__ l1_target, float l1_scale, float* __restrict__ grad2d) {
   __shared__ float4 s0[BATCH], s1[BATCH], s2[BATCH];
-  for (uint32_t tile = next_tile(work, true); tile < n_tiles; tile = next_tile(work, false))
-    raster_bwd_tile<TW, TH, BATCH>(tile, s0, s1, s2, records, values, ranges, views, n_views, t_ws,
-                                   ncontrib, d_image, d_tfinal, l1_image, l1_target, l1_scale,
-                                   grad2d);
+  for (uint32_t tile = next_tile(work, true); tile < n_tiles; tile = next_tile(work, false)) {
+    if (d_tfinal)
+      raster_bwd_tile<TW, TH, BATCH, true>(tile, s0, s1, s2, records, values, ranges, views,
+                                           n_views, t_ws, ncontrib, d_image, d_tfinal, l1_image,
+                                           l1_target, l1_scale, grad2d);
+    else
+      raster_bwd_tile<TW, TH, BATCH, false>(tile, s0, s1, s2, records, values, ranges, views,
+                                            n_views, t_ws, ncontrib, d_image, d_tfinal, l1_image,
+                                            l1_target, l1_scale, grad2d);
+  }
 }
 
 __global__ void reset_counter_kernel(uint32_t* __restrict__ c) {
