@@ -96,10 +96,12 @@ __device__ __forceinline__ bool record_hits_tile(const float4 r0, const float4 r
                             double(py1) + 0.5);
 }
 
-// Records whose conservative tile box holds more than kSmallBox candidates are
-// binned by the whole wavefront (lanes take consecutive candidates in
-// row-major order); smaller ones by their own lane.
-constexpr int kSmallBox = 16;
+// Records whose conservative tile box holds at most kSmallBox candidate tiles
+// go through their wavefront's flat candidate list, their hits kept as one
+// bit per candidate; larger ones are binned by bin_big_kernel, a workgroup
+// per record.
+constexpr int kSmallBox = 32;
+static_assert(kSmallBox <= 32, "hit masks are 32 bits");
 
 struct BinRec {
   float4 r0, r1;
