@@ -36,7 +36,8 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_tile_sort(unsigned long long* comp, const uint32_t* tile_counts,
                             const uint32_t* tile_end, const DevStatus* status,
                             unsigned long long* keys_out, uint32_t* vals_out, uint32_t* ranges,
-                            uint32_t n_tiles, int digit_bits, int rec_bits, hipStream_t st);
+                            uint32_t n_tiles, int digit_bits, int rec_bits, uint32_t* big_tiles,
+                            uint32_t* n_big_tiles, hipStream_t st);
 hipError_t launch_raster_fwd(int tw, int th, int batch, uint32_t persistent_blocks,
                              uint32_t* work, const float* records, const uint32_t* values,
                              const uint32_t* ranges, const DevView* views, int n_views,
@@ -201,7 +202,8 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.off_views = take(sizeof(DevView) * uint64_t(f->n_views > 0 ? f->n_views : 1));
   l.off_scenes = take(sizeof(DevScene) * uint64_t(f->n_scenes > 0 ? f->n_scenes : 1));
   l.pub.off_records = take(uint64_t(kRecFloats) * 4 * n_rec);
-  l.off_tile_counts = take(4 * (n_tiles + 1));
+  l.off_tile_counts = take(4 * (n_tiles + 2));
+  l.off_big_tiles = take(4 * n_tiles);
   l.off_tile_cursor = take(4 * n_tiles);
   l.off_hit_mask = take(4 * n_rec);
   l.off_big_list = take(4 * n_rec);
@@ -343,11 +345,13 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
   const unsigned long long cap = (unsigned long long)L.pub.pair_capacity;
   auto* comp = at<unsigned long long>(ws, L.off_comp);
   stage_mark(frame, UBS_STAGE_BIN_COUNT, 0, s);
-  // the word after the tile counts counts the records binned by workgroups
+  // the two words after the tile counts count the records binned by
+  // workgroups and the tiles sorted by workgroups
   uint32_t* big_count = tile_counts + n_tiles;
+  uint32_t* n_big_tiles = tile_counts + n_tiles + 1;
   uint32_t* big_list = at<uint32_t>(ws, L.off_big_list);
   // clear the counters; also add up preprocess's per-workgroup counts
-  UBS_HIP(launch_bin_prepare(tile_counts, size_t(n_tiles) + 1, at<uint32_t>(ws, L.off_pre_partials),
+  UBS_HIP(launch_bin_prepare(tile_counts, size_t(n_tiles) + 2, at<uint32_t>(ws, L.off_pre_partials),
                              pre_partials_used(p), uint32_t(L.n_pre_partials), status, s));
   uint32_t* hit_mask = at<uint32_t>(ws, L.off_hit_mask);
   UBS_HIP(launch_bin_count(records, views, frame->n_views, n_rec, tile_counts, hit_mask, big_list,
@@ -365,7 +369,8 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
   UBS_HIP(launch_tile_sort(comp, tile_counts, tile_cursor, status,
                            at<unsigned long long>(ws, L.pub.off_keys),
                            at<uint32_t>(ws, L.pub.off_values), at<uint32_t>(ws, L.pub.off_ranges),
-                           n_tiles, L.digit_bits, L.rec_bits, s));
+                           n_tiles, L.digit_bits, L.rec_bits, at<uint32_t>(ws, L.off_big_tiles),
+                           n_big_tiles, s));
   stage_mark(frame, UBS_STAGE_SORT, 1, s);
   return UBS_OK;
 }

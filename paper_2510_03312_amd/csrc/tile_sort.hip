@@ -9,9 +9,11 @@
 // (tile, depth) keys emitted in record order: depth first, equal depths in
 // record order.
 //
-// tile_sort_kernel: one workgroup per tile (grid-stride over tiles).
-//   n <= 256          rank sort: each key's position is the number of
-//                     smaller keys in the segment (LDS broadcast reads);
+// tile_sort_small_kernel: one wavefront per tile (grid-stride over tiles);
+//   writes every tile's range and sorts the segments of at most kSmallSort
+//   pairs by rank (each key's position is the number of smaller keys in the
+//   segment, LDS broadcast reads); larger tiles go to a list for
+// tile_sort_kernel: one workgroup per listed tile.
 //   n <= kLdsSortMax  bitonic sort in LDS, padded to a power of two;
 //   larger            LSD radix sort of the segment in global memory by the
 //                     workgroup alone (each wavefront owns a contiguous
@@ -27,6 +29,7 @@ namespace ubs {
 
 constexpr int kTileSortThreads = 256;
 constexpr int kLdsSortMax = 4096;   // keys held in LDS (32 KiB)
+constexpr uint32_t kSmallSort = 256;
 
 __device__ __forceinline__ void write_sorted(unsigned long long key, uint32_t tile, size_t pos,
                                              unsigned long long* __restrict__ keys_out,
@@ -117,37 +120,68 @@ __device__ unsigned long long* wg_radix_sort(unsigned long long* seg, unsigned l
   return src;
 }
 
-__global__ void __launch_bounds__(kTileSortThreads) tile_sort_kernel(
-    unsigned long long* __restrict__ comp, const uint32_t* __restrict__ tile_counts,
+__global__ void __launch_bounds__(64) tile_sort_small_kernel(
+    const unsigned long long* __restrict__ comp, const uint32_t* __restrict__ tile_counts,
     const uint32_t* __restrict__ tile_end, const DevStatus* __restrict__ status,
     unsigned long long* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-    uint32_t* __restrict__ ranges, uint32_t n_tiles, int digit_bits, int rec_bits) {
-  __shared__ unsigned long long s_keys[kLdsSortMax];
-  __shared__ uint32_t s_hist[4][256];
-  __shared__ uint32_t s_lds4[4];
-  __shared__ uint32_t s_flag;
+    uint32_t* __restrict__ ranges, uint32_t n_tiles, uint32_t* __restrict__ big_tiles,
+    uint32_t* __restrict__ n_big_tiles) {
+  __shared__ unsigned long long s_keys[kSmallSort];
+  constexpr int Q = int(kSmallSort / 64);
+  const uint32_t lane = threadIdx.x;
   const bool overflow = status->overflow != 0u;
   for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const uint32_t n = overflow ? 0u : tile_counts[t];
     const uint32_t end = n ? tile_end[t] : 0u;
     const uint32_t start = end - n;   // an empty tile's range is (0, 0)
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
       ranges[2 * size_t(t)] = start;
       ranges[2 * size_t(t) + 1] = end;
     }
     if (n == 0) continue;
-    if (n <= kTileSortThreads) {
-      const uint32_t i = threadIdx.x;
-      const unsigned long long k = i < n ? comp[start + i] : 0ull;
-      if (i < n) s_keys[i] = k;
-      __syncthreads();
-      if (i < n) {
-        uint32_t rank = 0;
-        for (uint32_t j = 0; j < n; ++j) rank += s_keys[j] < k ? 1u : 0u;
-        write_sorted(k, t, size_t(start) + rank, keys_out, vals_out);
-      }
-      __syncthreads();
-    } else if (n <= uint32_t(kLdsSortMax)) {
+    if (n > kSmallSort) {
+      if (lane == 0) big_tiles[atomicAdd(n_big_tiles, 1u)] = t;
+      continue;
+    }
+    unsigned long long k[Q];
+    uint32_t rank[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const uint32_t i = lane + 64u * uint32_t(q);
+      k[q] = i < n ? comp[start + i] : ~0ull;
+      if (i < n) s_keys[i] = k[q];
+      rank[q] = 0u;
+    }
+    __syncthreads();
+    for (uint32_t j = 0; j < n; ++j) {
+      const unsigned long long kj = s_keys[j];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) rank[q] += kj < k[q] ? 1u : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const uint32_t i = lane + 64u * uint32_t(q);
+      if (i < n) write_sorted(k[q], t, size_t(start) + rank[q], keys_out, vals_out);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kTileSortThreads) tile_sort_kernel(
+    unsigned long long* __restrict__ comp, const uint32_t* __restrict__ tile_counts,
+    const uint32_t* __restrict__ tile_end, const uint32_t* __restrict__ big_tiles,
+    const uint32_t* __restrict__ n_big_tiles, unsigned long long* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out, int digit_bits, int rec_bits) {
+  __shared__ unsigned long long s_keys[kLdsSortMax];
+  __shared__ uint32_t s_hist[4][256];
+  __shared__ uint32_t s_lds4[4];
+  __shared__ uint32_t s_flag;
+  const uint32_t n_big = *n_big_tiles;
+  for (uint32_t bt = blockIdx.x; bt < n_big; bt += gridDim.x) {
+    const uint32_t t = big_tiles[bt];
+    const uint32_t n = tile_counts[t];
+    const uint32_t start = tile_end[t] - n;
+    if (n <= uint32_t(kLdsSortMax)) {
       uint32_t P = 512;
       while (P < n) P <<= 1;
       for (uint32_t i = threadIdx.x; i < P; i += kTileSortThreads)
@@ -184,14 +218,20 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_sort_kernel(
   }
 }
 
+// big_tiles: n_tiles words; n_big_tiles must be zero.
 hipError_t launch_tile_sort(unsigned long long* comp, const uint32_t* tile_counts,
                             const uint32_t* tile_end, const DevStatus* status,
                             unsigned long long* keys_out, uint32_t* vals_out, uint32_t* ranges,
-                            uint32_t n_tiles, int digit_bits, int rec_bits, hipStream_t st) {
+                            uint32_t n_tiles, int digit_bits, int rec_bits, uint32_t* big_tiles,
+                            uint32_t* n_big_tiles, hipStream_t st) {
   if (n_tiles == 0) return hipSuccess;
   const uint32_t grid = n_tiles < 65536u ? n_tiles : 65536u;
-  hipLaunchKernelGGL(tile_sort_kernel, dim3(grid), dim3(kTileSortThreads), 0, st, comp,
-                     tile_counts, tile_end, status, keys_out, vals_out, ranges, n_tiles,
+  hipLaunchKernelGGL(tile_sort_small_kernel, dim3(grid), dim3(64), 0, st, comp, tile_counts,
+                     tile_end, status, keys_out, vals_out, ranges, n_tiles, big_tiles,
+                     n_big_tiles);
+  const uint32_t big_grid = n_tiles < 256u ? n_tiles : 256u;
+  hipLaunchKernelGGL(tile_sort_kernel, dim3(big_grid), dim3(kTileSortThreads), 0, st, comp,
+                     tile_counts, tile_end, big_tiles, n_big_tiles, keys_out, vals_out,
                      digit_bits, rec_bits);
   return hipGetLastError();
 }

@@ -83,7 +83,8 @@ static_assert(sizeof(DevStatus) == sizeof(ubs_status_block), "status block size"
 struct Layout {
   ubs_layout pub;
   uint64_t off_views, off_scenes, off_offsets, off_blocksums;
-  uint64_t off_tile_counts, off_tile_cursor;  // pairs per tile; segment cursors
+  uint64_t off_tile_counts, off_tile_cursor;  // pairs per tile (+2 counters); segment cursors
+  uint64_t off_big_tiles;            // tiles sorted by a workgroup (more than 256 pairs)
   uint64_t off_hit_mask;             // per record: hits among its candidate tiles
   uint64_t off_big_list;             // records binned by a workgroup each
   uint64_t off_comp;                 // emitted (depth bits << 32 | record) per tile segment
