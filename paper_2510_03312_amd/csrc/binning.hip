@@ -486,42 +486,69 @@ hipError_t launch_bin_count(const float* records, const DevView* views, int n_vi
   return hipGetLastError();
 }
 
-// Exclusive scan of up to kSingleScanMax values by one workgroup, chunk by
-// chunk with a running carry (one launch instead of three); same outputs as
-// the three-kernel scan.
+// Exclusive scan of up to kSingleScanMax values by one workgroup of 1024
+// threads, 8192 values per step with a running carry (one launch instead of
+// three); same outputs as the three-kernel scan.
 constexpr uint32_t kSingleScanMax = 16u * kScanTile;
+constexpr int kSingleThreads = 1024;
+constexpr int kSingleItems = 8;
+constexpr uint32_t kSingleChunk = uint32_t(kSingleThreads * kSingleItems);
 
-__global__ void __launch_bounds__(kScanThreads) scan_single_kernel(
+__global__ void __launch_bounds__(kSingleThreads) scan_single_kernel(
     const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ out,
     uint32_t* __restrict__ list, DevStatus* __restrict__ status, unsigned long long capacity,
     unsigned long long* __restrict__ total_out) {
-  __shared__ uint32_t lds[8];
-  __shared__ unsigned long long lds4[4];
+  constexpr int W = kSingleThreads / 64;
+  __shared__ uint32_t s_wave[W];
+  __shared__ unsigned long long s_wave64[W];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t carry = 0;
   unsigned long long total = 0;
-  for (uint32_t c0 = 0; c0 < n; c0 += kScanTile) {
-    const uint32_t base = c0 + threadIdx.x * kScanItems;
-    uint32_t vals[kScanItems];
-    uint32_t s = 0;
-    unsigned long long s64 = 0;
+  for (uint32_t c0 = 0; c0 < n; c0 += kSingleChunk) {
+    const uint32_t base = c0 + threadIdx.x * kSingleItems;
+    uint32_t vals[kSingleItems];
+    uint32_t sum = 0;
+    unsigned long long sum64 = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
+    for (int k = 0; k < kSingleItems; ++k) {
       vals[k] = base + k < n ? in[base + k] : 0u;
-      s += vals[k];
-      s64 += vals[k];
+      sum += vals[k];
+      sum64 += vals[k];
     }
-    uint32_t tot32;
-    uint32_t run = carry + block_exclusive_scan_u32(s, lds, &tot32);
-    total += block_sum_u64(s64, lds4);
+    // inclusive scan of the thread sums within the wavefront, and its total
+    // in 64 bits (a chunk's 32-bit sum may wrap; the 64-bit total may not)
+    uint32_t x = sum;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sum64 += __shfl_xor(sum64, o, 64);
+    if (lane == 63) s_wave[wave] = x;
+    if (lane == 0) s_wave64[wave] = sum64;
+    __syncthreads();
+    uint32_t before = 0, chunk = 0;
+    unsigned long long chunk64 = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint32_t t = s_wave[w];
+      before += w < wave ? t : 0u;
+      chunk += t;
+      chunk64 += s_wave64[w];
+    }
+    __syncthreads();
+    uint32_t run = carry + before + x - sum;
+#pragma unroll
+    for (int k = 0; k < kSingleItems; ++k) {
       if (base + k < n) {
         out[base + k] = run;
         if (list != nullptr && vals[k] != 0u) list[run] = base + k;
       }
       run += vals[k];
     }
-    carry += tot32;
+    carry += chunk;
+    total += chunk64;
   }
   if (threadIdx.x == 0 && status != nullptr) {
     status->pairs_needed = total;
@@ -534,8 +561,8 @@ static hipError_t scan_impl(const uint32_t* in, uint32_t n, uint32_t* tile_sums,
                             uint32_t* list, DevStatus* status, unsigned long long capacity,
                             hipStream_t st, unsigned long long* total_out) {
   if (n <= kSingleScanMax) {
-    hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kScanThreads), 0, st, in, n, out, list,
-                       status, capacity, total_out);
+    hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kSingleThreads), 0, st, in, n, out,
+                       list, status, capacity, total_out);
     return hipGetLastError();
   }
   const uint32_t n_tiles = (n + kScanTile - 1) / kScanTile;
