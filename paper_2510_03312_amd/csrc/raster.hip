@@ -96,13 +96,19 @@ __device__ __forceinline__ void raster_fwd_tile(
   const int px = tx * TW + lane % TW;
   const int py0 = ty * TH + lane / TW;
   const float fx = float(px) + 0.5f;
+  // T: transmittance; a pixel that has stopped keeps it negated, so that
+  // every later record fails its T (1 - alpha) >= 1e-4 test (instead of the
+  // pixel's state being tested on every record); |T| is the final value
   float T[PPL], cr[PPL], cg[PPL], cb[PPL];
   uint32_t last[PPL];
   uint32_t done = 0;   // bit k: pixel k has stopped (or lies outside the image)
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     T[k] = 1.0f; cr[k] = cg[k] = cb[k] = 0.0f; last[k] = 0;
-    if (px >= V.W || py0 + k * RSTEP >= V.H) done |= 1u << k;
+    if (px >= V.W || py0 + k * RSTEP >= V.H) {
+      done |= 1u << k;
+      T[k] = -1.0f;
+    }
   }
   constexpr uint32_t kAll = (PPL == 32) ? 0xffffffffu : ((1u << PPL) - 1u);
   const uint32_t start = ranges[2 * size_t(tile)], end = ranges[2 * size_t(tile) + 1];
@@ -123,11 +129,10 @@ __device__ __forceinline__ void raster_fwd_tile(
     if (done == kAll) continue;
     const int nb = int(min(uint32_t(BATCH), end - b0));
     for (int j = 0; j < nb; ++j) {
-      const float4 g0 = s0[j], g1 = s1[j];
+      const float4 g0 = s0[j], g1 = s1[j], g2 = s2[j];
       const ColTerms ct = col_terms(g0, fx - g0.x);
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
-        if (done & (1u << k)) continue;
         const float dy = float(py0 + k * RSTEP) + 0.5f - g0.y;
         const float r = eval_r(ct, g1.x, dy);
         if (!(r <= g1.y)) continue;
@@ -136,8 +141,11 @@ __device__ __forceinline__ void raster_fwd_tile(
         const float alpha = fminf(kAlphaMax, sigma);
         if (alpha < kAlphaMin) continue;
         const float test = T[k] * (1.0f - alpha);
-        if (test < kTStop) { done |= 1u << k; continue; }
-        const float4 g2 = s2[j];
+        if (test < kTStop) {
+          done |= 1u << k;
+          T[k] = -fabsf(T[k]);
+          continue;
+        }
         const float w = alpha * T[k];
         cr[k] += g2.x * w;
         cg[k] += g2.y * w;
@@ -156,8 +164,8 @@ __device__ __forceinline__ void raster_fwd_tile(
       image[3 * pix] = cr[k];
       image[3 * pix + 1] = cg[k];
       image[3 * pix + 2] = cb[k];
-      t_ws[pix] = T[k];
-      if (t_user) t_user[pix] = T[k];
+      t_ws[pix] = fabsf(T[k]);
+      if (t_user) t_user[pix] = fabsf(T[k]);
       ncontrib[pix] = last[k];
     }
   }
