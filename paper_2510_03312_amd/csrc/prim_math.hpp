@@ -26,6 +26,11 @@ template <> __device__ __forceinline__ double m_exp<double>(double x) { return e
 template <typename T> __device__ __forceinline__ T m_sqrt(T x);
 template <> __device__ __forceinline__ float m_sqrt<float>(float x) { return sqrtf(x); }
 template <> __device__ __forceinline__ double m_sqrt<double>(double x) { return sqrt(x); }
+// 1 / sqrt(x): where both sqrt(x) and its reciprocal are needed, sqrt(x) is
+// taken as x * rsqrt(x) (one library call instead of a root and a division)
+template <typename T> __device__ __forceinline__ T m_rsqrt(T x);
+template <> __device__ __forceinline__ float m_rsqrt<float>(float x) { return rsqrtf(x); }
+template <> __device__ __forceinline__ double m_rsqrt<double>(double x) { return rsqrt(x); }
 
 // Scalar factors of the opacity (the modulation terms, o(q), beta_x, rho)
 // are well conditioned in their arguments, so they are evaluated in float32
@@ -126,7 +131,7 @@ __device__ __forceinline__ void geo_forward(const Raw<C, ROT>& r, Geo<T, C, ROT>
   if (ROT == UBS_ROT_QUAT) {
     T w = r.rq[0], x = r.rq[1], y = r.rq[2], z = r.rq[3];
     T nn = w * w + x * x + y * y + z * z;
-    T inv = T(1) / m_sqrt<T>(nn);
+    T inv = m_rsqrt<T>(nn);
     if (!(nn > T(0))) g.ok = false;
     w *= inv; x *= inv; y *= inv; z *= inv;
     R[0][0] = T(1) - T(2) * (y * y + z * z);
@@ -186,9 +191,9 @@ __device__ __forceinline__ void geo_forward(const Raw<C, ROT>& r, Geo<T, C, ROT>
 #pragma unroll
       for (int k = 0; k < j; ++k) d -= g.Lh[j][k] * g.Lh[j][k];
       if (!(d > T(0))) { g.ok = false; d = T(1); }
-      T ljj = m_sqrt<T>(d);
-      g.Lh[j][j] = ljj;
-      T inv = T(1) / ljj;
+      T inv = m_rsqrt<T>(d);
+      g.Lh[j][j] = d * inv;
+      g.Li[j][j] = inv;
 #pragma unroll
       for (int i = j + 1; i < C; ++i) {
         T acc = Sq[i][j];
@@ -205,11 +210,11 @@ __device__ __forceinline__ void geo_forward(const Raw<C, ROT>& r, Geo<T, C, ROT>
 #pragma unroll
       for (int i = 0; i < C; ++i) {
         if (i < j) { g.Li[i][j] = T(0); continue; }
-        if (i == j) { g.Li[i][i] = T(1) / g.Lh[i][i]; continue; }
+        if (i == j) continue;   // 1 / Lh[i][i], set by the factorisation
         T acc = T(0);
 #pragma unroll
         for (int k = j; k < i; ++k) acc += g.Lh[i][k] * g.Li[k][j];
-        g.Li[i][j] = -acc / g.Lh[i][i];
+        g.Li[i][j] = -acc * g.Li[i][i];
       }
     }
 #pragma unroll
@@ -255,8 +260,9 @@ __device__ __forceinline__ void view_forward(const Raw<C, ROT>& r, const Geo<T, 
     for (int b = 0; b < 3; ++b) Sc[a][b] = g.Sx[a][b];
   if constexpr (C > 0) {
     T dv[3] = {T(r.mu[0]) - T(V.cam[0]), T(r.mu[1]) - T(V.cam[1]), T(r.mu[2]) - T(V.cam[2])};
-    T dist = m_sqrt<T>(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-    T inv = T(1) / dist;
+    T dd = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
+    T inv = m_rsqrt<T>(dd);
+    T dist = dd * inv;
     s.dist = dist;
 #pragma unroll
     for (int k = 0; k < 3; ++k) s.dir[k] = dv[k] * inv;
@@ -742,9 +748,8 @@ __device__ __forceinline__ void geo_backward(const Raw<C, ROT>& r, const Geo<T, 
     out[pr.log_s + j] = float(acc);
   }
   if (ROT == UBS_ROT_QUAT) {
-    T qn = m_sqrt<T>(T(r.rq[0]) * T(r.rq[0]) + T(r.rq[1]) * T(r.rq[1]) + T(r.rq[2]) * T(r.rq[2]) +
-                     T(r.rq[3]) * T(r.rq[3]));
-    T iq = T(1) / qn;
+    T iq = m_rsqrt<T>(T(r.rq[0]) * T(r.rq[0]) + T(r.rq[1]) * T(r.rq[1]) +
+                      T(r.rq[2]) * T(r.rq[2]) + T(r.rq[3]) * T(r.rq[3]));
     T w = T(r.rq[0]) * iq, x = T(r.rq[1]) * iq, y = T(r.rq[2]) * iq, z = T(r.rq[3]) * iq;
     T gw = T(2) * (-z * GR[0][1] + y * GR[0][2] + z * GR[1][0] - x * GR[1][2] - y * GR[2][0] + x * GR[2][1]);
     T gx = T(2) * (y * GR[0][1] + z * GR[0][2] + y * GR[1][0] - T(2) * x * GR[1][1] - w * GR[1][2] +
