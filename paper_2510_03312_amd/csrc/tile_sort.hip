@@ -30,6 +30,7 @@ namespace ubs {
 constexpr int kTileSortThreads = 256;
 constexpr int kLdsSortMax = 4096;   // keys held in LDS (32 KiB)
 constexpr uint32_t kSmallSort = 256;
+static_assert(kSmallSort == 256, "the rank sort counts for up to four 64-key slots");
 
 __device__ __forceinline__ void write_sorted(unsigned long long key, uint32_t tile, size_t pos,
                                              unsigned long long* __restrict__ keys_out,
@@ -120,6 +121,17 @@ __device__ unsigned long long* wg_radix_sort(unsigned long long* seg, unsigned l
   return src;
 }
 
+// rank[q] += number of keys in s_keys[0, n) below k[q], for the first NQ slots
+template <int NQ>
+__device__ __forceinline__ void count_smaller(const unsigned long long* s_keys, uint32_t n,
+                                              const unsigned long long* k, uint32_t* rank) {
+  for (uint32_t j = 0; j < n; ++j) {
+    const unsigned long long kj = s_keys[j];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) rank[q] += kj < k[q] ? 1u : 0u;
+  }
+}
+
 __global__ void __launch_bounds__(64) tile_sort_small_kernel(
     const unsigned long long* __restrict__ comp, const uint32_t* __restrict__ tile_counts,
     const uint32_t* __restrict__ tile_end, const DevStatus* __restrict__ status,
@@ -153,10 +165,12 @@ __global__ void __launch_bounds__(64) tile_sort_small_kernel(
       rank[q] = 0u;
     }
     __syncthreads();
-    for (uint32_t j = 0; j < n; ++j) {
-      const unsigned long long kj = s_keys[j];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) rank[q] += kj < k[q] ? 1u : 0u;
+    // only the slots holding keys count (n <= 64 * nq)
+    switch ((n + 63u) / 64u) {
+      case 1: count_smaller<1>(s_keys, n, k, rank); break;
+      case 2: count_smaller<2>(s_keys, n, k, rank); break;
+      case 3: count_smaller<3>(s_keys, n, k, rank); break;
+      default: count_smaller<4>(s_keys, n, k, rank); break;
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
