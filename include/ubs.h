@@ -3,7 +3,8 @@
  *
  * The library renders N-dimensional anisotropic Beta primitives (the
  * paper's Section 4: N = 3 + C with C query dimensions; C = 0 static 3-D,
- * C = 3 view direction "UBS-6D", C = 4 time + view direction "UBS-7D")
+ * C = 3 view direction "UBS-6D", C = 4 time + view direction "UBS-7D",
+ * C = 5..7 the 7-D query extended by values each view supplies)
  * through a differentiable tile rasteriser, and returns the gradient of a
  * loss with respect to every primitive parameter.
  *
@@ -53,7 +54,7 @@ extern "C" {
 typedef enum {
   UBS_OK = 0,
   UBS_ERR_ARG = 1,          /* invalid argument (null pointer, size, enum) */
-  UBS_ERR_UNSUPPORTED = 2,  /* valid but unsupported (e.g. C > 4, tile shape) */
+  UBS_ERR_UNSUPPORTED = 2,  /* valid but unsupported (e.g. C = 1, 2, tile shape) */
   UBS_ERR_CAPACITY = 3,     /* workspace too small for the frame */
   UBS_ERR_HIP = 4           /* a HIP runtime call failed */
 } ubs_status;
@@ -65,12 +66,14 @@ typedef enum {
 } ubs_rot;
 
 /*
- * A scene: n primitives of dimension dim = 3 + C (0 <= C <= 4).
+ * A scene: n primitives of dimension dim = 3 + C, dim in {3, 6, 7, 8, 9, 10}
+ * (C = 1, 2 have no query defined here: UBS_ERR_UNSUPPORTED).
  *
  * params: float32 [F][n], component-major (row r holds component r of every
  * primitive, primitive i at params[r * n + i]).  Rows, in order:
  *   mu_x     3          spatial mean (world units)
- *   mu_q     C          query mean; for C = 4 the order is [t, d0, d1, d2]
+ *   mu_q     C          query mean; for C >= 4 the order is
+ *                       [t, d0, d1, d2, e0, ..., e_{C-5}] (see ubs_view)
  *   rot      4 | 3      quaternion (w,x,y,z) | skew vector w
  *   log_s_x  3          log spatial scales (s_x = exp)
  *   L_qx     3C         the C x 3 block L_qx, row-major
@@ -81,7 +84,8 @@ typedef enum {
  *   o        1          opacity in [0, 1] (already activated)
  *   rgb      3          colour (already activated)
  * F = 3 + C + (4|3) + 3 + 3C + C(C+1)/2 + 1 + C + 1 + 3
- *   (35 for UBS-6D and 44 for UBS-7D with the skew rotation; +1 with quats).
+ *   (35 for UBS-6D and 44 for UBS-7D with the skew rotation; +1 with quats;
+ *   at most 78, for dim 10 with quaternions).
  * The covariance is Sigma = L L^T with L = [[R_x diag(s_x), 0], [L_qx, L_q]].
  *
  * dparams: float32 [F][n] in the same layout; ubs_render_bwd OVERWRITES it
@@ -89,7 +93,7 @@ typedef enum {
  * calls other than ubs_render_bwd.  Must not alias params.
  */
 typedef struct {
-  int32_t dim;            /* 3..7 */
+  int32_t dim;            /* 3, 6, 7, 8, 9, 10 */
   int32_t rot;            /* ubs_rot */
   int64_t n;              /* number of primitives, >= 0 */
   const float* params;    /* device [F][n] */
@@ -102,9 +106,12 @@ typedef struct {
  *   pixel (u, v) = (fx p_x / p_z + cx, fy p_y / p_z + cy);
  *   pixel (i, j) covers [i, i+1) x [j, j+1), sampled at its centre
  *   (i + 0.5, j + 0.5).
- * The query of a primitive in this view is q = d (C = 3) or q = [time, d]
- * (C = 4), where d is the unit direction from the camera centre -R^T t to
- * the primitive's spatial mean (world frame).  time is ignored unless C = 4.
+ * The query of a primitive in this view is q = d (C = 3), q = [time, d]
+ * (C = 4) or q = [time, d, query[0], ..., query[C - 5]] (C = 5..7: the
+ * paper's query holds any further non-spatial dimensions; their values come
+ * with the view), where d is the unit direction from the camera centre
+ * -R^T t to the primitive's spatial mean (world frame).  time is ignored
+ * unless C >= 4, query[k] unless C > 4 + k; all must be finite.
  */
 typedef struct {
   int32_t scene;          /* index into the scene array */
@@ -114,7 +121,7 @@ typedef struct {
   float t[3];
   float fx, fy, cx, cy;
   float time;
-  float _pad1[3];
+  float query[3];         /* query values beyond [time, d] (dim 8-10) */
 } ubs_view;               /* 96 bytes */
 
 /*

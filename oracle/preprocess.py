@@ -11,6 +11,7 @@ from __future__ import annotations
 import math
 from typing import Dict, Optional
 
+import numpy as np
 import torch
 
 F64 = torch.float64
@@ -134,11 +135,14 @@ def camera_center(view) -> torch.Tensor:
 
 
 def query(mu_x: torch.Tensor, view, C: int) -> torch.Tensor:
-    """Query vector per primitive, [n,C].
+    """Query vector per primitive, [n,C] (Section 4.1: q holds the
+    non-spatial dimensions, view direction, time, etc.).
 
     Reading: d is the unit direction from the camera centre to the
     (unconditioned) spatial mean, in world coordinates; for 7-D the query is
-    [t, d] with the view's timestamp t.
+    [t, d] with the view's timestamp t; for N > 7 the further query values
+    come with the view (its ``query`` attribute, zeros if absent) and follow:
+    [t, d, e_0, ..., e_{N-8}].
     """
     n = mu_x.shape[1]
     if C == 0:
@@ -147,10 +151,16 @@ def query(mu_x: torch.Tensor, view, C: int) -> torch.Tensor:
     d = v / torch.linalg.norm(v, dim=1, keepdim=True)
     if C == 3:
         return d
-    if C == 4:
+    if C >= 4:
         t = torch.full((n, 1), float(view.time), dtype=F64)
-        return torch.cat([t, d], 1)
-    raise ValueError("the camera query is defined for 6-D and 7-D; pass q explicitly")
+        parts = [t, d]
+        if C > 4:
+            e = np.zeros(C - 4)
+            given = np.asarray(getattr(view, "query", ()), dtype=np.float64).ravel()[:C - 4]
+            e[:given.size] = given
+            parts.append(torch.as_tensor(e, dtype=F64)[None, :].expand(n, C - 4))
+        return torch.cat(parts, 1)
+    raise ValueError("the camera query is defined for N = 3 and N >= 6; pass q explicitly")
 
 
 # --------------------------------------------------------------------------

@@ -41,7 +41,7 @@ class UbsScene(ctypes.Structure):
 class UbsView(ctypes.Structure):
     _fields_ = [("scene", c_int32), ("width", c_int32), ("height", c_int32), ("_pad0", c_int32),
                 ("R", c_float * 9), ("t", c_float * 3), ("fx", c_float), ("fy", c_float),
-                ("cx", c_float), ("cy", c_float), ("time", c_float), ("_pad1", c_float * 3)]
+                ("cx", c_float), ("cy", c_float), ("time", c_float), ("query", c_float * 3)]
 
 
 class UbsTuning(ctypes.Structure):

@@ -127,8 +127,8 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   uint64_t n_prims = 0, n_grad_compact = 0;
   for (int s = 0; s < f->n_scenes; ++s) {
     const ubs_scene& S = f->scenes[s];
-    if (S.dim < 3 || S.dim > 7) return UBS_ERR_ARG;
-    if (S.dim == 4 || S.dim == 5) return UBS_ERR_UNSUPPORTED;
+    if (S.dim < 3 || S.dim > kMaxDim) return UBS_ERR_ARG;
+    if (!dim_ok(S.dim)) return UBS_ERR_UNSUPPORTED;
     if (S.rot != UBS_ROT_QUAT && S.rot != UBS_ROT_SKEW) return UBS_ERR_ARG;
     if (S.n < 0 || S.n > int64_t(0x7fffffff)) return UBS_ERR_ARG;
     if (S.n > 0 && !S.params) return UBS_ERR_ARG;
@@ -157,12 +157,14 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
     if (!(V.fx > 0.0f) || !(V.fy > 0.0f) || !finite_f(V.fx) || !finite_f(V.fy) ||
         !finite_f(V.cx) || !finite_f(V.cy) || !finite_f(V.time))
       return UBS_ERR_ARG;
+    for (int k = 0; k < 3; ++k) if (!finite_f(V.query[k])) return UBS_ERR_ARG;
     DevView d{};
     memcpy(d.R, V.R, sizeof(d.R));
     memcpy(d.t, V.t, sizeof(d.t));
     for (int k = 0; k < 3; ++k)  // camera centre -R^T t
       d.cam[k] = -(double(V.R[k]) * V.t[0] + double(V.R[3 + k]) * V.t[1] + double(V.R[6 + k]) * V.t[2]);
     d.fx = V.fx; d.fy = V.fy; d.cx = V.cx; d.cy = V.cy; d.time = V.time;
+    for (int k = 0; k < 3; ++k) d.query[k] = V.query[k];
     d.scene = V.scene;
     d.W = V.width; d.H = V.height;
     d.tile_w = tu.tile_w; d.tile_h = tu.tile_h;
@@ -278,7 +280,7 @@ extern "C" {
 int32_t ubs_abi_version(void) { return UBS_ABI_VERSION; }
 
 int32_t ubs_param_count(int32_t dim, int32_t rot) {
-  if (dim != 3 && dim != 6 && dim != 7) return 0;
+  if (!dim_ok(dim)) return 0;
   if (rot != UBS_ROT_QUAT && rot != UBS_ROT_SKEW) return 0;
   return param_rows(dim - 3, rot).F;
 }

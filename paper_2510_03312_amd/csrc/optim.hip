@@ -16,7 +16,7 @@
 
 namespace ubs {
 
-constexpr int kAdamMaxRows = 64;
+constexpr int kAdamMaxRows = kMaxRows;
 
 enum : uint8_t { kRegNone = 0, kRegOpacity = 1, kRegScale = 2, kRegNoise = 3 };
 
@@ -110,9 +110,9 @@ extern "C" ubs_status ubs_adam_step(const ubs_adam* cfg, int32_t dim, int32_t ro
                                     float* params, const float* dparams, float* m, float* v,
                                     const float* noise, void* stream) {
   if (!cfg) return UBS_ERR_ARG;
-  if (dim < 3 || dim > 7 || (rot != UBS_ROT_QUAT && rot != UBS_ROT_SKEW) || n < 0)
+  if (dim < 3 || dim > kMaxDim || (rot != UBS_ROT_QUAT && rot != UBS_ROT_SKEW) || n < 0)
     return UBS_ERR_ARG;
-  if (dim == 4 || dim == 5) return UBS_ERR_UNSUPPORTED;
+  if (!dim_ok(dim)) return UBS_ERR_UNSUPPORTED;
   if (cfg->step < 1 || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
       !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps >= 0.0f))
     return UBS_ERR_ARG;

@@ -114,11 +114,11 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int sce
     view_forward<T, C, ROT>(r, g, V, s);
     view_backward<T, C, ROT>(r, g, V, s, gr, G);
   }
-  const ParamRows pr = param_rows(C, ROT);
-  float out[64];
+  constexpr int F = param_rows(C, ROT).F;
+  float out[F];
   geo_backward<T, C, ROT>(r, g, G, out);
 #pragma unroll
-  for (int k = 0; k < pr.F; ++k) compact[int64_t(k) * S.n + t] = out[k];
+  for (int k = 0; k < F; ++k) compact[int64_t(k) * S.n + t] = out[k];
 }
 
 // dparams[k, i] = compact[k, offs[i]] for live primitives, 0 otherwise.  One
@@ -182,10 +182,16 @@ static hipError_t pre_fwd_dispatch(const DevScene& S, int scene, const DevView* 
     if (C == 0) return pre_fwd_t<T, 0, 0>(S, scene, views, n_views, records, live, partial, stride, st);
     if (C == 3) return pre_fwd_t<T, 3, 0>(S, scene, views, n_views, records, live, partial, stride, st);
     if (C == 4) return pre_fwd_t<T, 4, 0>(S, scene, views, n_views, records, live, partial, stride, st);
+    if (C == 5) return pre_fwd_t<T, 5, 0>(S, scene, views, n_views, records, live, partial, stride, st);
+    if (C == 6) return pre_fwd_t<T, 6, 0>(S, scene, views, n_views, records, live, partial, stride, st);
+    if (C == 7) return pre_fwd_t<T, 7, 0>(S, scene, views, n_views, records, live, partial, stride, st);
   } else {
     if (C == 0) return pre_fwd_t<T, 0, 1>(S, scene, views, n_views, records, live, partial, stride, st);
     if (C == 3) return pre_fwd_t<T, 3, 1>(S, scene, views, n_views, records, live, partial, stride, st);
     if (C == 4) return pre_fwd_t<T, 4, 1>(S, scene, views, n_views, records, live, partial, stride, st);
+    if (C == 5) return pre_fwd_t<T, 5, 1>(S, scene, views, n_views, records, live, partial, stride, st);
+    if (C == 6) return pre_fwd_t<T, 6, 1>(S, scene, views, n_views, records, live, partial, stride, st);
+    if (C == 7) return pre_fwd_t<T, 7, 1>(S, scene, views, n_views, records, live, partial, stride, st);
   }
   return hipErrorInvalidValue;
 }
@@ -201,10 +207,16 @@ static hipError_t pre_bwd_dispatch(const DevScene& S, int scene, const DevView* 
     if (C == 0) return pre_bwd_t<T, 0, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
     if (C == 3) return pre_bwd_t<T, 3, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
     if (C == 4) return pre_bwd_t<T, 4, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
+    if (C == 5) return pre_bwd_t<T, 5, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
+    if (C == 6) return pre_bwd_t<T, 6, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
+    if (C == 7) return pre_bwd_t<T, 7, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
   } else {
     if (C == 0) return pre_bwd_t<T, 0, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
     if (C == 3) return pre_bwd_t<T, 3, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
     if (C == 4) return pre_bwd_t<T, 4, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
+    if (C == 5) return pre_bwd_t<T, 5, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
+    if (C == 6) return pre_bwd_t<T, 6, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
+    if (C == 7) return pre_bwd_t<T, 7, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
   }
   return hipErrorInvalidValue;
 }

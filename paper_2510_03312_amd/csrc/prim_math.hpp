@@ -4,7 +4,8 @@
 //   Sigma = L L^T with L = [[R_x diag(s_x), 0], [L_qx, L_q]]
 //     -> Sigma_x = M M^T, Sigma_xq = M L_qx^T, Sigma_q = L_qx L_qx^T + L_q L_q^T
 //        (M = R_x diag(s_x))
-//   q = d or [t, d], d = unit(mu_x - camera centre); v = q - mu_q
+//   q = d, [t, d] or [t, d, e] (e: the view's query values beyond 7-D),
+//   d = unit(mu_x - camera centre); v = q - mu_q
 //   Lhat = chol(Sigma_q); w = Lhat^-1 v;
 //   o(q) = o prod_i (1 - tanh(w_i^2))^(4 exp(b_qi))
 //   bt_i = min(exp(b_qi), 1); K = Sigma_xq Sigma_q^-1
@@ -267,8 +268,10 @@ __device__ __forceinline__ void view_forward(const Raw<C, ROT>& r, const Geo<T, 
 #pragma unroll
     for (int k = 0; k < 3; ++k) s.dir[k] = dv[k] * inv;
     T q[Cdim<C>::V];
-    if constexpr (C == 4) {
+    if constexpr (C >= 4) {   // [t, d, query values of the view beyond 7-D]
       q[0] = T(V.time); q[1] = s.dir[0]; q[2] = s.dir[1]; q[3] = s.dir[2];
+#pragma unroll
+      for (int k = 4; k < C; ++k) q[k] = T(V.query[k - 4]);
     } else if constexpr (C == 3) {
       q[0] = s.dir[0]; q[1] = s.dir[1]; q[2] = s.dir[2];
     } else {
@@ -594,7 +597,7 @@ __device__ __forceinline__ void view_backward(const Raw<C, ROT>& r, const Geo<T,
 #pragma unroll
     for (int k = 0; k < C; ++k) G.muq[k] -= gv[k];
     T gd[3] = {T(0), T(0), T(0)};
-    if constexpr (C == 4) { gd[0] = gv[1]; gd[1] = gv[2]; gd[2] = gv[3]; }
+    if constexpr (C >= 4) { gd[0] = gv[1]; gd[1] = gv[2]; gd[2] = gv[3]; }
     else if constexpr (C == 3) { gd[0] = gv[0]; gd[1] = gv[1]; gd[2] = gv[2]; }
     else {
 #pragma unroll

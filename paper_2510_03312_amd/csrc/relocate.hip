@@ -213,9 +213,9 @@ extern "C" ubs_status ubs_relocate(int32_t dim, int32_t rot, int64_t n, float* p
                                    float* v, const double* uniforms, float o_min, void* ws,
                                    uint64_t ws_bytes, uint64_t* ws_bytes_needed,
                                    uint32_t* targets_out, uint64_t* n_dead_out, void* stream) {
-  if (dim < 3 || dim > 7 || (rot != UBS_ROT_QUAT && rot != UBS_ROT_SKEW) || n < 0)
+  if (dim < 3 || dim > kMaxDim || (rot != UBS_ROT_QUAT && rot != UBS_ROT_SKEW) || n < 0)
     return UBS_ERR_ARG;
-  if (dim == 4 || dim == 5) return UBS_ERR_UNSUPPORTED;
+  if (!dim_ok(dim)) return UBS_ERR_UNSUPPORTED;
   if (n > (int64_t(1) << 31) - 1) return UBS_ERR_UNSUPPORTED;
   if (!(o_min >= 0.0f)) return UBS_ERR_ARG;
   const RelocLayout L = reloc_layout(n);

@@ -24,6 +24,7 @@ struct DevView {
   float cam[3];          // camera centre -R^T t
   float fx, fy, cx, cy;
   float time;
+  float query[3];        // query values beyond [t, d] (dim 8-10)
   int32_t scene;
   int32_t W, H;
   int32_t tiles_x, tiles_y;
@@ -31,7 +32,7 @@ struct DevView {
   uint32_t tile_base;    // first global tile of the view
   uint32_t rec_base;     // first record of the view
   uint32_t pix_base;     // first pixel of the view
-  uint32_t _pad[2];
+  uint32_t _pad[3];
 };
 static_assert(sizeof(DevView) % 16 == 0, "DevView alignment");
 
@@ -49,8 +50,8 @@ struct ParamRows {
   int mu_x, mu_q, rot, log_s, lqx, lq, b_x, b_q, o, rgb, F;
 };
 
-__host__ __device__ inline ParamRows param_rows(int C, int rot) {
-  ParamRows r;
+__host__ __device__ constexpr ParamRows param_rows(int C, int rot) {
+  ParamRows r{};
   int k = 0;
   r.mu_x = k; k += 3;
   r.mu_q = k; k += C;
@@ -64,6 +65,14 @@ __host__ __device__ inline ParamRows param_rows(int C, int rot) {
   r.rgb = k; k += 3;
   r.F = k;
   return r;
+}
+
+// Supported dimensions N: 3 (static), 6 (+ view direction), 7 (+ time) and
+// 8 .. kMaxDim (+ query values given with each view).
+constexpr int kMaxDim = 10;
+constexpr int kMaxRows = param_rows(kMaxDim - 3, UBS_ROT_QUAT).F;
+__host__ __device__ constexpr bool dim_ok(int dim) {
+  return dim == 3 || (dim >= 6 && dim <= kMaxDim);
 }
 
 // Status block, mirrors ubs_status_block.

@@ -57,6 +57,8 @@ def _view_to_c(v) -> UbsView:
     c.t = (ctypes.c_float * 3)(*t)
     c.fx, c.fy, c.cx, c.cy = float(v.fx), float(v.fy), float(v.cx), float(v.cy)
     c.time = float(getattr(v, "time", 0.0))
+    extra = [float(x) for x in getattr(v, "query", ())][:3]
+    c.query = (ctypes.c_float * 3)(*(extra + [0.0] * (3 - len(extra))))
     return c
 
 

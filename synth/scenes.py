@@ -12,7 +12,8 @@ this order, with ``C = dim - 3`` query dimensions:
 field                 rows         notes
 ====================  ===========  =========================================
 ``mu_x``              3            spatial mean (world units)
-``mu_q``              C            query mean; 7-D order is ``[t, d0, d1, d2]``
+``mu_q``              C            query mean; 7-D order is ``[t, d0, d1, d2]``,
+                                   N > 7 appends the view's extra query values
 ``rot``               4 or 3       quaternion ``(w, x, y, z)`` or skew ``w``
 ``log_s_x``           3            log of the spatial scales
 ``L_qx``              3*C          C x 3 block, row-major
@@ -79,6 +80,7 @@ class ViewSpec:
     cx: float
     cy: float
     time: float = 0.0
+    query: tuple = (0.0, 0.0, 0.0)   # query values beyond [t, d] (N > 7)
 
 
 def look_at_view(center, width: int, height: int, *, scene: int = 0,
@@ -130,15 +132,19 @@ def make_scene(dim: int, n: int, seed: int, *, dist: str = "cfg0",
         rows.append(rng.uniform(-1.0, 1.0, size=(3, n)))
     else:
         rows.append(rng.normal(0.0, 1.5, size=(3, n)))
-    # mu_q: [t, d] for 7-D, d for 6-D, generic U(0, 1) otherwise
+    # mu_q: [t, d] for 7-D, d for 6-D, [t, d, extra U(0, 1)] beyond 7-D,
+    # generic U(0, 1) otherwise
     if c > 0:
         mq = np.empty((c, n))
         k = 0
-        if c == 4:
+        if c >= 4:
             mq[0] = rng.uniform(0.0, 1.0, size=n)
             k = 1
         if c - k == 3:
             mq[k:] = _normalize_rows(rng.normal(0.0, 1.0, size=(3, n)))
+        elif c > 4:
+            mq[1:4] = _normalize_rows(rng.normal(0.0, 1.0, size=(3, n)))
+            mq[4:] = rng.uniform(0.0, 1.0, size=(c - 4, n))
         else:
             mq[k:] = rng.uniform(0.0, 1.0, size=(c - k, n))
         rows.append(mq)
@@ -158,7 +164,7 @@ def make_scene(dim: int, n: int, seed: int, *, dist: str = "cfg0",
         for i in range(c):
             for j in range(i + 1):
                 if i == j:
-                    if c == 4 and i == 0:
+                    if c >= 4 and i == 0:
                         lq[k] = np.log(rng.uniform(0.02, 0.5, size=n))
                     else:
                         lq[k] = np.log(rng.uniform(0.2, 2.0, size=n))

@@ -38,9 +38,11 @@ def test_library_exports_every_declared_entry_point():
 
 def test_abi_version_and_param_counts():
     assert _lib.ubs_abi_version() == 1
-    for dim in (3, 6, 7):
+    for dim in (3, 6, 7, 8, 9, 10):
         for rot in (0, 1):
             assert _lib.ubs_param_count(dim, rot) == param_count(dim, rot)
+    assert _lib.ubs_param_count(10, 0) == 78
+    assert _lib.ubs_param_count(11, 0) == 0
     assert _lib.ubs_param_count(6, 1) == 35
     assert _lib.ubs_param_count(7, 1) == 44
     assert _lib.ubs_param_count(5, 0) == 0
@@ -50,7 +52,7 @@ def test_ctypes_structs_match_the_header(tmp_path):
     prog = tmp_path / "sz.c"
     fields = {
         "ubs_scene": ["dim", "rot", "n", "params", "dparams"],
-        "ubs_view": ["scene", "width", "height", "R", "t", "fx", "fy", "cx", "cy", "time"],
+        "ubs_view": ["scene", "width", "height", "R", "t", "fx", "fy", "cx", "cy", "time", "query"],
         "ubs_tuning": ["tile_w", "tile_h", "batch_depth", "digit_bits", "pair_capacity", "flags"],
         "ubs_frame": ["scenes", "n_scenes", "n_views", "views", "tuning", "stage_events"],
         "ubs_layout": ["bytes", "n_records", "n_tiles", "n_pixels", "pair_capacity", "key_bits",
@@ -130,12 +132,13 @@ def test_size_query_without_gpu():
     (lambda f: setattr(f.c.tuning, "batch_depth", 96), _lib.UBS_ERR_UNSUPPORTED),
     (lambda f: setattr(f.c.tuning, "pair_capacity", -1), _lib.UBS_ERR_ARG),
     (lambda f: setattr(f._sc[0], "dim", 5), _lib.UBS_ERR_UNSUPPORTED),
-    (lambda f: setattr(f._sc[0], "dim", 9), _lib.UBS_ERR_ARG),
+    (lambda f: setattr(f._sc[0], "dim", 11), _lib.UBS_ERR_ARG),
     (lambda f: setattr(f._sc[0], "rot", 3), _lib.UBS_ERR_ARG),
     (lambda f: setattr(f._sc[0], "params", None), _lib.UBS_ERR_ARG),
     (lambda f: setattr(f._vw[0], "scene", 4), _lib.UBS_ERR_ARG),
     (lambda f: setattr(f._vw[0], "width", 0), _lib.UBS_ERR_ARG),
     (lambda f: setattr(f._vw[0], "fx", float("nan")), _lib.UBS_ERR_ARG),
+    (lambda f: f._vw[0].query.__setitem__(2, float("inf")), _lib.UBS_ERR_ARG),
     (lambda f: setattr(f.c, "n_scenes", -1), _lib.UBS_ERR_ARG),
 ])
 def test_argument_errors_are_reported_before_launch(mutate, code):
@@ -179,7 +182,7 @@ def test_empty_frame_is_valid():
     (dict(beta2=-0.1), _lib.UBS_ERR_ARG),
     (dict(eps=-1.0), _lib.UBS_ERR_ARG),
     (dict(dim=5), _lib.UBS_ERR_UNSUPPORTED),
-    (dict(dim=8), _lib.UBS_ERR_ARG),
+    (dict(dim=11), _lib.UBS_ERR_ARG),
     (dict(rot=2), _lib.UBS_ERR_ARG),
     (dict(n=-1), _lib.UBS_ERR_ARG),
     (dict(params=0), _lib.UBS_ERR_ARG),

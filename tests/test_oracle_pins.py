@@ -271,6 +271,87 @@ def test_zero_cross_correlation_and_flat_query_reduce_to_3d(dim):
     np.testing.assert_allclose(rN["t_final"], r3["t_final"], atol=1e-12)
 
 
+def _extend_7d(P7, rot, extra_mu, extra_logs, extra_b):
+    """An N-D scene (N = 7 + m) from a 7-D one: m further query dimensions
+    uncorrelated with everything else (zero rows in L_qx, zero off-diagonal
+    entries of L_q), with the given means, log scales and Beta shapes."""
+    m = len(extra_mu)
+    s7, sN = pp.field_slices(7, rot), pp.field_slices(7 + m, rot)
+    n = P7.shape[1]
+    P = np.zeros((pp.n_params(7 + m, rot), n))
+    for k in ("mu_x", "rot", "log_s_x", "b_x", "o", "rgb"):
+        P[sN[k]] = P7[s7[k]]
+    P[sN["mu_q"]] = np.concatenate([P7[s7["mu_q"]], np.repeat(np.asarray(extra_mu)[:, None], n, 1)])
+    P[sN["b_q"]] = np.concatenate([P7[s7["b_q"]], np.repeat(np.asarray(extra_b)[:, None], n, 1)])
+    qx7 = P7[s7["L_qx"]].reshape(4, 3, n)
+    qx = np.zeros((4 + m, 3, n))
+    qx[:4] = qx7
+    P[sN["L_qx"]] = qx.reshape(3 * (4 + m), n)
+    rows, k7 = [], 0   # L_q lower triangle, row-major
+    lq7 = P7[s7["L_q"]]
+    for i in range(4 + m):
+        for j in range(i + 1):
+            if i < 4:
+                rows.append(lq7[k7]); k7 += 1
+            elif i == j:
+                rows.append(np.full(n, extra_logs[i - 4]))
+            else:
+                rows.append(np.zeros(n))
+    P[sN["L_q"]] = np.stack(rows)
+    return P
+
+
+@pytest.mark.parametrize("m,rot", [(1, 0), (3, 1)])
+def test_extra_query_dimensions_at_their_mean_reduce_to_7d(m, rot):
+    """Query dimensions beyond [t, d] that are uncorrelated with the others
+    and queried at their mean leave every record of the 7-D primitive
+    unchanged: their block of Sigma_q^-1 does not couple (K gains zero
+    columns) and each opacity factor is (1 - tanh 0)^beta = 1."""
+    sc = make_scene(7, 400, seed=31 + m, dist="cfg3", rot=rot)
+    P7 = sc.params.astype(np.float64)
+    extra = [0.25, -0.4, 0.7][:m]
+    P = _extend_7d(P7, rot, extra, [np.log(0.6), np.log(1.3), np.log(0.2)][:m], [0.8, -0.5, 0.1][:m])
+    view = make_view(160, 120, time=0.45)
+    view.query = tuple(extra) + (0.0,) * (3 - m)
+    r7 = pp.preprocess(torch.as_tensor(P7), 7, rot, view)
+    rN = pp.preprocess(torch.as_tensor(P), 7 + m, rot, view)
+    assert torch.equal(r7["valid"], rN["valid"])
+    np.testing.assert_allclose(rN["rec"].numpy(), r7["rec"].numpy(), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("m", [1, 2])
+def test_extra_query_dimension_off_its_mean_scales_the_opacity(m):
+    """Off its mean, an uncorrelated further query dimension with scale s and
+    shape b multiplies o(q) by (1 - tanh(w^2))^(4 e^b), w = (q_e - mu_e) / s
+    (Section 4.3), and changes neither the conditioned mean nor the
+    covariance (hence the projected mean and conic)."""
+    sc = make_scene(7, 300, seed=41 + m, dist="cfg3", rot=0)
+    P7 = sc.params.astype(np.float64)
+    sl7 = pp.field_slices(7, 0)
+    P7[sl7["mu_x"]] = np.random.default_rng(m).uniform(-1, 1, size=(3, 300))
+    P7[sl7["o"]] = 0.9
+    P7[sl7["b_q"]] = -6.0   # nearly flat in [t, d], so that most records survive
+    mu_e, s_e, b_e = [0.1, 0.9][:m], [0.5, 2.0][:m], [0.3, -0.7][:m]
+    P = _extend_7d(P7, 0, mu_e, list(np.log(s_e)), b_e)
+    view = make_view(160, 120, time=0.6)
+    q_e = [0.45, 0.2][:m]
+    view.query = tuple(q_e) + (0.0,) * (3 - m)
+    r7 = pp.preprocess(torch.as_tensor(P7), 7, 0, view)
+    rN = pp.preprocess(torch.as_tensor(P), 7 + m, 0, view)
+    factor = 1.0
+    for k in range(m):
+        w = (q_e[k] - mu_e[k]) / s_e[k]
+        factor *= (1.0 - math.tanh(w * w)) ** (4.0 * math.exp(b_e[k]))
+    both = (r7["valid"] & rN["valid"]).numpy()
+    assert both.sum() > 50
+    a, b = rN["rec"].numpy()[both], r7["rec"].numpy()[both]
+    np.testing.assert_allclose(a[:, [0, 1, 2, 3, 4, 7, 8, 9, 10, 11]],
+                               b[:, [0, 1, 2, 3, 4, 7, 8, 9, 10, 11]], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(a[:, 6], b[:, 6] * factor, rtol=1e-12)
+    # rho follows o(q): 1 - (255 o(q))^(-1/beta_x)
+    np.testing.assert_allclose(a[:, 5], 1.0 - (255.0 * a[:, 6]) ** (-1.0 / a[:, 7]), rtol=1e-10)
+
+
 def test_zero_cross_block_leaves_spatial_part_unchanged():
     sc, f, Sigma = _random_full(6, 30, 17)
     Sg = Sigma.clone()
@@ -569,7 +650,8 @@ def _fd_check(P, dim, rot, view, rng, n_check=40, h_rel=1e-6, variant=()):
     assert checked >= n_check // 2
 
 
-@pytest.mark.parametrize("dim,rot,dist", [(3, 0, "cfg0"), (6, 1, "cfg1"), (7, 0, "cfg3"), (6, 0, "cfg1")])
+@pytest.mark.parametrize("dim,rot,dist", [(3, 0, "cfg0"), (6, 1, "cfg1"), (7, 0, "cfg3"), (6, 0, "cfg1"),
+                                          (8, 0, "cfg3"), (10, 1, "cfg3")])
 def test_oracle_gradient_matches_finite_differences(dim, rot, dist):
     rng = np.random.default_rng(dim * 10 + rot)
     sc = make_scene(dim, 60, seed=dim + rot, dist=dist, rot=rot)
@@ -581,6 +663,7 @@ def test_oracle_gradient_matches_finite_differences(dim, rot, dist):
     if dim > 3:
         P[sl["b_q"]] = rng.uniform(-1.0, 1.0, size=(dim - 3, sc.n))
     view = make_view(32, 24, time=0.4)
+    view.query = (0.3, 0.6, 0.1)
     _fd_check(P, dim, rot, view, rng)
 
 
