@@ -58,6 +58,8 @@ WORKLOADS = {
     "cfg2": ("cfg2", "1,000,000 6-D Beta primitives, one 1920x1080 view, forward+backward, L1 loss"),
     "cfg1": ("cfg1", "500,000 6-D Beta primitives, one 1264x832 view, forward only"),
     "cfg0": ("cfg0", "2,000 3-D Beta primitives, one 128x128 view, forward+backward, L1 loss"),
+    "dim10": ("dim10", "1,000,000 10-D Beta primitives (query [t, d, e0..e2], e from the view), "
+                       "one 1920x1080 view at t=0.5, forward+backward, L1 loss"),
     "cfg3": ("cfg3", "2,000,000 7-D Beta primitives, 8 views of 1352x1014 (cameras on a circle, "
                      "t = k/7) in one batched frame, forward+backward, L1 loss"),
     "cfg4": ("cfg4", "4 scenes of 7-D Beta primitives (100k/500k/1.5M/3M), 32 views of uneven "

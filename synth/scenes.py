@@ -29,6 +29,8 @@ scenes stand in for them, at the paper's primitive counts):
 
 * ``cfg0``: 2,000 static 3-D primitives, 128x128, camera at z = -4.
 * ``cfg1``: 500,000 6-D primitives, 1264x832, forward only.
+* ``dim10``: 1,000,000 10-D primitives (the 7-D query plus three values
+  given by the view), 1920x1080, forward and backward.
 * ``cfg2``: 1,000,000 6-D primitives, 1920x1080, forward and backward.
 * ``headline``: 1,000,000 7-D primitives, 1920x1080, t = 0.5, fwd+bwd.
 * ``cfg3``: 2,000,000 7-D primitives, 8 views of 1352x1014 on a circle.
@@ -190,7 +192,7 @@ def make_target(height: int, width: int, seed: int = 1) -> np.ndarray:
     return rng.uniform(0.0, 1.0, size=(height, width, 3)).astype(np.float32)
 
 
-CONFIG_NAMES = ("cfg0", "cfg1", "cfg2", "headline", "cfg3", "cfg4")
+CONFIG_NAMES = ("cfg0", "cfg1", "cfg2", "headline", "cfg3", "cfg4", "dim10")
 
 
 def make_config(name: str, *, n: Optional[int] = None, width: Optional[int] = None,
@@ -223,6 +225,16 @@ def make_config(name: str, *, n: Optional[int] = None, width: Optional[int] = No
         sc = make_scene(7, n or 1_000_000, 0, dist="cfg3", rot=rot)
         W, H = width or 1920, height or 1080
         views = [make_view(W, H, time=0.5)]
+        mode = "fwdbwd"
+        scenes = [sc]
+    elif name == "dim10":
+        # beyond 7-D: the headline's 1M primitives with three further query
+        # dimensions whose values come with the view
+        sc = make_scene(10, n or 1_000_000, 0, dist="cfg3", rot=rot)
+        W, H = width or 1920, height or 1080
+        v = make_view(W, H, time=0.5)
+        v.query = (0.2, 0.7, 0.5)
+        views = [v]
         mode = "fwdbwd"
         scenes = [sc]
     elif name == "cfg3":
