@@ -16,7 +16,7 @@ hipError_t launch_bin_prepare(uint32_t* words, size_t n_words, const uint32_t* p
                               uint32_t n_partials, uint32_t stride, DevStatus* status,
                               hipStream_t st);
 hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const DevView* views,
-                                 int n_views, const float* records, const float* grad2d,
+                                 int n_views, const float* records, float* grad2d,
                                  const uint32_t* live, const uint32_t* offs, const uint32_t* list,
                                  const unsigned long long* n_live, float* compact, hipStream_t st);
 hipError_t launch_scan_compact(const uint32_t* flags, uint32_t n, uint32_t* tile_sums,

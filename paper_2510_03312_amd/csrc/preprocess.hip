@@ -79,6 +79,31 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
   }
 }
 
+// The backward raster leaves per record the pixel sums of
+//   P = sum dx s', Q = sum dy s', U = sum dx^2 s', V = sum dx dy s',
+//   E = sum dy^2 s', with s' = sigma (d loss / d alpha) / (1 - r),
+//   A_o = sum sigma d loss / d alpha, A_b = sum that times log2(1 - r),
+// and the colour sums (dx, dy: pixel centre minus projected mean).  With
+// d sigma / d r = -beta sigma / (1 - r), r = a dx^2 + 2 b dx dy + c dy^2,
+// d sigma / d o = sigma / o and d sigma / d beta = sigma ln(1 - r), the
+// record-field gradients are
+//   d/d mx = 2 beta (a P + b Q), d/d my = 2 beta (b P + c Q),
+//   d/d a = -beta U, d/d b = -2 beta V, d/d c = -beta E,
+//   d/d o = A_o / o, d/d beta = ln 2 A_b
+// (in place; rec: the record as the raster used it).
+__device__ __forceinline__ void record_gradient_from_sums(const float* __restrict__ rec,
+                                                          float* g) {
+  const float a = rec[2], b = rec[3], c = rec[4], o = rec[6], beta = rec[7];
+  const float P = g[0], Q = g[1], U = g[2], V = g[3], E = g[4];
+  g[0] = 2.0f * beta * (a * P + b * Q);
+  g[1] = 2.0f * beta * (b * P + c * Q);
+  g[2] = -beta * U;
+  g[3] = -2.0f * beta * V;
+  g[4] = -beta * E;
+  g[5] = g[5] / o;
+  g[6] = g[6] * 0.69314718f;
+}
+
 // Thread t runs the adjoint of the t-th live primitive of the compacted list
 // and writes its gradient to column t of the compacted [F][n] buffer
 // (coalesced); scatter_dparams_kernel moves it to the primitive's column.
@@ -87,7 +112,7 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int sce
                                                              const DevView* __restrict__ views,
                                                              int n_views,
                                                              const float* __restrict__ records,
-                                                             const float* __restrict__ grad2d,
+                                                             float* __restrict__ grad2d,
                                                              const uint32_t* __restrict__ list,
                                                              const unsigned long long* __restrict__ n_live,
                                                              float* __restrict__ compact) {
@@ -105,11 +130,15 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int sce
     if (V.scene != scene) continue;
     const size_t rec = size_t(V.rec_base) + size_t(i);
     // the forward wrote rho > 0 exactly for the records it kept
-    if (!(records[rec * kRecFloats + 5] > 0.0f)) continue;
+    const float* rp = records + rec * kRecFloats;
+    if (!(rp[5] > 0.0f)) continue;
     float gr[kGradFloats];
-    const float* gp = grad2d + rec * kGradFloats;
+    float* gp = grad2d + rec * kGradFloats;
 #pragma unroll
     for (int k = 0; k < kGradFloats; ++k) gr[k] = gp[k];
+    record_gradient_from_sums(rp, gr);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) gp[k] = gr[k];
     ViewState<T, C> s;
     view_forward<T, C, ROT>(r, g, V, s);
     view_backward<T, C, ROT>(r, g, V, s, gr, G);
@@ -162,7 +191,7 @@ static hipError_t pre_fwd_t(const DevScene& S, int scene, const DevView* views, 
 
 template <typename T, int C, int ROT>
 static hipError_t pre_bwd_t(const DevScene& S, int scene, const DevView* views, int n_views,
-                            const float* records, const float* grad2d, const uint32_t* live,
+                            const float* records, float* grad2d, const uint32_t* live,
                             const uint32_t* offs, const uint32_t* list,
                             const unsigned long long* n_live, float* compact, hipStream_t st) {
   const unsigned blocks = unsigned((S.n + 255) / 256);
@@ -198,7 +227,7 @@ static hipError_t pre_fwd_dispatch(const DevScene& S, int scene, const DevView* 
 
 template <typename T>
 static hipError_t pre_bwd_dispatch(const DevScene& S, int scene, const DevView* views, int n_views,
-                                   const float* records, const float* grad2d, const uint32_t* live,
+                                   const float* records, float* grad2d, const uint32_t* live,
                                    const uint32_t* offs, const uint32_t* list,
                                    const unsigned long long* n_live, float* compact,
                                    hipStream_t st) {
@@ -232,7 +261,7 @@ hipError_t launch_preprocess_fwd(bool fp64, const DevScene& S, int scene, const 
 }
 
 hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const DevView* views,
-                                 int n_views, const float* records, const float* grad2d,
+                                 int n_views, const float* records, float* grad2d,
                                  const uint32_t* live, const uint32_t* offs, const uint32_t* list,
                                  const unsigned long long* n_live, float* compact, hipStream_t st) {
   if (S.n == 0) return hipSuccess;

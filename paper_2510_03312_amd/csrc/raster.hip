@@ -315,12 +315,10 @@ __device__ __forceinline__ void raster_bwd_tile(
       const float4 g0 = s0[j], g1 = s1[j], g2 = s2[j];
       const float dx = fx - g0.x;
       const ColTerms ct = col_terms(g0, dx);
-      // per-lane sums over the lane's pixels, with the factors common to a
-      // record (1/o, ln 2, -beta) applied after the sums:
+      // per-lane sums over the lane's pixels (the factors common to a record,
+      // 1/o, ln 2 and -beta, are applied by the per-primitive adjoint):
       //   a_o = sum s,  a_be = sum s log2(1 - r),  a_dr = sum s / (1 - r)
-      //   (a_dry, a_dryy: times dy, dy^2) with s = sigma d loss / d alpha;
-      //   d sigma / d o = sigma / o, d sigma / d beta = sigma ln(1 - r),
-      //   d sigma / d r = -beta sigma / (1 - r)
+      //   (a_dry, a_dryy: times dy, dy^2) with s = sigma d loss / d alpha
       // (zeros the compiler cannot rematerialise: otherwise it re-creates
       // them on every path that skips the first pixel's update)
       float a_r, a_g, a_b, a_o, a_be, a_dr, a_dry, a_dryy;
@@ -367,22 +365,19 @@ __device__ __forceinline__ void raster_bwd_tile(
         T[k] = Ti;
       }
       if (__ballot(any) == 0ull) continue;
-      // record-field gradients of this lane: r = a dx^2 + 2 b dx dy + c dy^2,
-      // d r sums = -beta (a_dr, a_dry, a_dryy)
-      const float b = 0.5f * g0.w;
-      const float nb = -g1.w, nb2 = -2.0f * g1.w;
-      const float A = nb * a_dr, D = nb * a_dry;
+      // the record's pixel sums (P, Q, U, V, E, A_o, A_b, colour): the
+      // per-primitive adjoint turns them into record-field gradients
       float gv[kGradFloats];
-      gv[0] = -2.0f * (g0.z * dx * A + b * D);
-      gv[1] = -2.0f * (b * dx * A + g1.x * D);
-      gv[2] = dx * dx * A;
-      gv[3] = nb2 * dx * a_dry;
-      gv[4] = nb * a_dryy;
-      gv[6] = a_be * 0.69314718f;
+      gv[0] = dx * a_dr;
+      gv[1] = a_dry;
+      gv[2] = dx * gv[0];
+      gv[3] = dx * a_dry;
+      gv[4] = a_dryy;
+      gv[5] = a_o;
+      gv[6] = a_be;
       gv[7] = a_r;
       gv[8] = a_g;
       gv[9] = a_b;
-      gv[5] = a_o * hw_exp2(-g1.z);   // times 1 / o
       // sums over the wavefront: halves folded onto each other (permlane32
       // swap: field 2p in lanes 0-31, 2p+1 in lanes 32-63), row pairs folded
       // (permlane16 swap: one field per row), DPP sums within the rows;
