@@ -78,7 +78,7 @@ __global__ void upload_views_kernel(ViewChunk c, DevView* __restrict__ dst,
 __global__ void fill_f32_kernel(float* __restrict__ p, size_t n) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const size_t stride = size_t(gridDim.x) * blockDim.x;
-  for (size_t k = i; k < n; k += stride) p[k] = 0.0f;
+  for (size_t k = i; k < n; k += stride) store_stream(&p[k], 0.0f);
 }
 
 // Records a stage event on the call's stream.

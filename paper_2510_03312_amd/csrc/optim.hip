@@ -95,9 +95,9 @@ __global__ void __launch_bounds__(256) adam_kernel_vec4(AdamRows rows, AdamScala
     p.z += a.lambda_eps * e.z;
     p.w += a.lambda_eps * e.w;
   }
-  reinterpret_cast<float4*>(params)[row4 + j] = p;
-  reinterpret_cast<float4*>(m)[row4 + j] = mm;
-  reinterpret_cast<float4*>(v)[row4 + j] = vv;
+  store_stream(reinterpret_cast<float4*>(params) + row4 + j, p);
+  store_stream(reinterpret_cast<float4*>(m) + row4 + j, mm);
+  store_stream(reinterpret_cast<float4*>(v) + row4 + j, vv);
 }
 
 }  // namespace ubs

@@ -53,9 +53,9 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
     }
     const size_t rec = size_t(V.rec_base) + size_t(i);
     float4* rp = reinterpret_cast<float4*>(records + rec * kRecFloats);
-    rp[0] = o0;
-    rp[1] = o1;
-    rp[2] = o2;
+    store_stream(&rp[0], o0);
+    store_stream(&rp[1], o1);
+    store_stream(&rp[2], o2);
   }
   if (active) live[i] = visible > 0 ? 1u : 0u;
   // per-workgroup counts (no atomics on a shared word: those serialise across
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(256) scatter_dparams_kernel(DevScene S,
 #pragma unroll
     for (int q = 0; q < kScatterChunk; ++q) {
       const int k = k0 + q;
-      if (k < S.F) S.dparams[int64_t(k) * S.n + i] = v[q];
+      if (k < S.F) store_stream(&S.dparams[int64_t(k) * S.n + i], v[q]);
     }
   }
 }
