@@ -65,8 +65,9 @@ __device__ __forceinline__ void load_raw(const float* __restrict__ P, int64_t n,
                                          Raw<C, ROT>& r) {
   const ParamRows pr = param_rows(C, ROT);
   bool fin = true;
+  // streaming loads: each parameter is read once per launch
   auto ld = [&](int row) {
-    const float x = P[int64_t(row) * n + i];
+    const float x = __builtin_nontemporal_load(&P[int64_t(row) * n + i]);
     fin = fin && isfinite(x);
     return x;
   };
