@@ -56,13 +56,14 @@ __global__ void __launch_bounds__(256) adam_kernel(AdamRows rows, AdamScalars a,
   for (int k = 0; k < kAdamItems; ++k) {
     const int64_t i = i0 + int64_t(k) * 256;
     if (i >= n) break;
-    float mm = m[row + i], vv = v[row + i];
-    float q = adam_one(params[row + i], dparams[row + i], mm, vv, step, kind, a);
+    float mm = load_stream(m + row + i), vv = load_stream(v + row + i);
+    float q = adam_one(load_stream(params + row + i), load_stream(dparams + row + i), mm, vv, step,
+                       kind, a);
     // the spatial-mean rows are rows 0-2, noise row r is noise[r * n ...]
     if (kind == kRegNoise && a.has_noise) q += a.lambda_eps * noise[row + i];
-    params[row + i] = q;
-    m[row + i] = mm;
-    v[row + i] = vv;
+    store_stream(params + row + i, q);
+    store_stream(m + row + i, mm);
+    store_stream(v + row + i, vv);
   }
 }
 
@@ -80,16 +81,16 @@ __global__ void __launch_bounds__(256) adam_kernel_vec4(AdamRows rows, AdamScala
   const uint8_t kind = rows.kind[r];
   const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;   // float4 index in the row
   if (j >= n / 4) return;
-  float4 p = reinterpret_cast<const float4*>(params)[row4 + j];
-  const float4 g = reinterpret_cast<const float4*>(dparams)[row4 + j];
-  float4 mm = reinterpret_cast<const float4*>(m)[row4 + j];
-  float4 vv = reinterpret_cast<const float4*>(v)[row4 + j];
+  float4 p = load_stream(reinterpret_cast<const float4*>(params) + row4 + j);
+  const float4 g = load_stream(reinterpret_cast<const float4*>(dparams) + row4 + j);
+  float4 mm = load_stream(reinterpret_cast<const float4*>(m) + row4 + j);
+  float4 vv = load_stream(reinterpret_cast<const float4*>(v) + row4 + j);
   p.x = adam_one(p.x, g.x, mm.x, vv.x, step, kind, a);
   p.y = adam_one(p.y, g.y, mm.y, vv.y, step, kind, a);
   p.z = adam_one(p.z, g.z, mm.z, vv.z, step, kind, a);
   p.w = adam_one(p.w, g.w, mm.w, vv.w, step, kind, a);
   if (kind == kRegNoise && a.has_noise) {
-    const float4 e = reinterpret_cast<const float4*>(noise)[row4 + j];
+    const float4 e = load_stream(reinterpret_cast<const float4*>(noise) + row4 + j);
     p.x += a.lambda_eps * e.x;
     p.y += a.lambda_eps * e.y;
     p.z += a.lambda_eps * e.z;

@@ -194,14 +194,14 @@ __global__ void __launch_bounds__(kRelThreads) reloc_apply_kernel(
       val = float(1.0 - pow(1.0 - double(o_keep[j]), 1.0 / (double(counts[j]) + 1.0)));
     else
       val = params[row + j];
-    params[row + i] = val;
-    m[row + i] = 0.0f;
-    v[row + i] = 0.0f;
+    store_stream(params + row + i, val);
+    store_stream(m + row + i, 0.0f);
+    store_stream(v + row + i, 0.0f);
   } else if (counts[i] > 0u) {
     if (r == o_row)
       params[row + i] = float(1.0 - pow(1.0 - double(o_keep[i]), 1.0 / (double(counts[i]) + 1.0)));
-    m[row + i] = 0.0f;
-    v[row + i] = 0.0f;
+    store_stream(m + row + i, 0.0f);
+    store_stream(v + row + i, 0.0f);
   }
 }
 

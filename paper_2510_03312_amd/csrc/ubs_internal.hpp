@@ -67,13 +67,20 @@ __host__ __device__ constexpr ParamRows param_rows(int C, int rot) {
   return r;
 }
 
-// Streaming stores (non-temporal hint): for data this launch does not read
-// again, so that it does not displace cached data on its way to HBM.
+// Streaming loads and stores (non-temporal hint): for data a launch reads or
+// writes once, so that it does not displace cached data on its way to or
+// from HBM.
 typedef float stream_f4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void store_stream(float* p, float v) { __builtin_nontemporal_store(v, p); }
 __device__ __forceinline__ void store_stream(uint32_t* p, uint32_t v) { __builtin_nontemporal_store(v, p); }
 __device__ __forceinline__ void store_stream(float4* p, float4 v) {
   __builtin_nontemporal_store(stream_f4{v.x, v.y, v.z, v.w}, reinterpret_cast<stream_f4*>(p));
+}
+
+__device__ __forceinline__ float load_stream(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float4 load_stream(const float4* p) {
+  const stream_f4 v = __builtin_nontemporal_load(reinterpret_cast<const stream_f4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
 }
 
 // Supported dimensions N: 3 (static), 6 (+ view direction), 7 (+ time) and
