@@ -13,7 +13,9 @@
 // Two stencil kernels, each over 16 x 16 tiles with an LDS patch of
 // (16 + 10)^2 pixels per channel and separable passes:
 //   ssim_fwd  statistics, S, the three partials (times -lambda / n) to the
-//             workspace, per-tile sums of S and |x - y|
+//             workspace (nine planes of all pixels: partial k of channel c
+//             in plane 3 c + k, so the backward's patch rows are contiguous),
+//             per-tile sums of S and |x - y|
 //   ssim_bwd  the window over the partials, the L1 term, d_image
 // and one workgroup adds the per-tile sums into the loss.
 #include <cmath>
@@ -29,6 +31,7 @@ constexpr int kSsimP = kSsimTile + 2 * kSsimR;   // 26
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
 constexpr int kSsimViewChunk = 64;
+constexpr int kSsimTmpW = kSsimTile + 1;   // padded row of the row-pass buffer (LDS banks)
 
 struct SsimView {
   int32_t W, H, tiles_x;
@@ -61,40 +64,65 @@ __device__ __forceinline__ int ssim_view_of_tile(const SsimView* __restrict__ vi
   return lo;
 }
 
-// Separable window over an LDS patch: rows first (kSsimP rows x 16 columns),
-// then columns; NQ quantities at once.  in[q][kSsimP][kSsimP], tmp[q][kSsimP][16].
+// Separable window over an LDS patch, NQ quantities at once: rows first
+// (kSsimP rows x 16 columns into tmp), then columns (16 x 16, left in
+// in[q][r][c] for r, c < 16, from where each thread reads its pixel).  A
+// thread computes 8 consecutive outputs from 18 consecutive inputs held in
+// registers (a sliding window), so each output costs about 2.3 LDS reads
+// instead of 11.  in[q][kSsimP][kSsimP], tmp[q][kSsimP][kSsimTmpW].
+constexpr int kSsimRun = 8;                       // outputs per thread and pass
+constexpr int kSsimSpan = kSsimRun + 2 * kSsimR;  // 18 inputs per run
+
 template <int NQ>
-__device__ __forceinline__ void window_16x16(const float (*in)[kSsimP][kSsimP],
-                                             float (*tmp)[kSsimP][kSsimTile], const SsimTaps& t,
+__device__ __forceinline__ void window_16x16(float (*in)[kSsimP][kSsimP],
+                                             float (*tmp)[kSsimP][kSsimTmpW], const SsimTaps& t,
                                              float* out) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < kSsimP * kSsimTile; e += 256) {
-    const int r = e / kSsimTile, c = e % kSsimTile;
+  constexpr int kRuns = kSsimTile / kSsimRun;     // 2 runs per row or column
+  // rows: task = (q, r, run)
+  for (int task = tid; task < NQ * kSsimP * kRuns; task += 256) {
+    const int q = task / (kSsimP * kRuns), rem = task % (kSsimP * kRuns);
+    const int r = rem / kRuns, c0 = (rem % kRuns) * kSsimRun;
+    float v[kSsimSpan];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
+    for (int k = 0; k < kSsimSpan; ++k) v[k] = in[q][r][c0 + k];
+#pragma unroll
+    for (int o = 0; o < kSsimRun; ++o) {
       float acc = 0.0f;
 #pragma unroll
-      for (int k = 0; k <= 2 * kSsimR; ++k) acc += t.g[k] * in[q][r][c + k];
-      tmp[q][r][c] = acc;
+      for (int k = 0; k <= 2 * kSsimR; ++k) acc += t.g[k] * v[o + k];
+      tmp[q][r][c0 + o] = acc;
+    }
+  }
+  __syncthreads();
+  // columns: task = (q, c, run), results into in[q][r][c]
+  for (int task = tid; task < NQ * kSsimTile * kRuns; task += 256) {
+    const int q = task / (kSsimTile * kRuns), rem = task % (kSsimTile * kRuns);
+    const int c = rem % kSsimTile, r0 = (rem / kSsimTile) * kSsimRun;
+    float v[kSsimSpan];
+#pragma unroll
+    for (int k = 0; k < kSsimSpan; ++k) v[k] = tmp[q][r0 + k][c];
+#pragma unroll
+    for (int o = 0; o < kSsimRun; ++o) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int k = 0; k <= 2 * kSsimR; ++k) acc += t.g[k] * v[o + k];
+      in[q][r0 + o][c] = acc;
     }
   }
   __syncthreads();
   const int r = tid / kSsimTile, c = tid % kSsimTile;
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    float acc = 0.0f;
-#pragma unroll
-    for (int k = 0; k <= 2 * kSsimR; ++k) acc += t.g[k] * tmp[q][r + k][c];
-    out[q] = acc;
-  }
+  for (int q = 0; q < NQ; ++q) out[q] = in[q][r][c];
 }
 
 __global__ void __launch_bounds__(256) ssim_fwd_kernel(
     const SsimView* __restrict__ views, int n_views, const float* __restrict__ image,
     const float* __restrict__ target, SsimTaps taps, float scale,
-    float* __restrict__ dstat, double* __restrict__ tile_sums) {
+    float* __restrict__ dstat, uint32_t n_pixels, double* __restrict__ tile_sums) {
   __shared__ float s_in[5][kSsimP][kSsimP];      // x, y, xx, yy, xy
-  __shared__ float s_tmp[5][kSsimP][kSsimTile];
+  __shared__ float s_tmp[5][kSsimP][kSsimTmpW];
+  __shared__ float s_px[2][kSsimP * kSsimP][3];  // the patch of image and target, RGB
   __shared__ double s_red[2][4];
   const uint32_t tile = blockIdx.x;
   const SsimView& V = views[ssim_view_of_tile(views, n_views, tile)];
@@ -105,18 +133,31 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(
   const int px = tx * kSsimTile + tid % kSsimTile, py = ty * kSsimTile + tid / kSsimTile;
   const bool inside = px < V.W && py < V.H;
   const size_t pix = size_t(V.pix_base) + size_t(py) * V.W + px;
+  // the patch's three channels at once (one 12-byte pixel per lane)
+  for (int e = tid; e < kSsimP * kSsimP; e += 256) {
+    const int r = e / kSsimP, c = e % kSsimP;
+    const int gx = x0 + c, gy = y0 + r;
+    float a[3] = {0.0f, 0.0f, 0.0f}, b[3] = {0.0f, 0.0f, 0.0f};
+    if (gx >= 0 && gx < V.W && gy >= 0 && gy < V.H) {
+      const size_t q = size_t(V.pix_base) + size_t(gy) * V.W + gx;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        a[ch] = image[3 * q + ch];
+        b[ch] = target[3 * q + ch];
+      }
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      s_px[0][e][ch] = a[ch];
+      s_px[1][e][ch] = b[ch];
+    }
+  }
   double s_sum = 0.0, l1_sum = 0.0;
   for (int ch = 0; ch < 3; ++ch) {
     __syncthreads();
     for (int e = tid; e < kSsimP * kSsimP; e += 256) {
       const int r = e / kSsimP, c = e % kSsimP;
-      const int gx = x0 + c, gy = y0 + r;
-      float a = 0.0f, b = 0.0f;
-      if (gx >= 0 && gx < V.W && gy >= 0 && gy < V.H) {
-        const size_t q = size_t(V.pix_base) + size_t(gy) * V.W + gx;
-        a = image[3 * q + ch];
-        b = target[3 * q + ch];
-      }
+      const float a = s_px[0][e][ch], b = s_px[1][e][ch];
       s_in[0][r][c] = a;
       s_in[1][r][c] = b;
       s_in[2][r][c] = a * a;
@@ -137,12 +178,13 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(
       const float d_m = 2.0f * my * (a2 - a1) * ib - 2.0f * mx * S * (1.0f / b1 - 1.0f / b2);
       const float d_sxx = -S / b2;
       const float d_sxy = 2.0f * a1 * ib;
-      float* d = dstat + 9 * pix + 3 * ch;
+      float* d = dstat + size_t(3 * ch) * n_pixels + pix;
       d[0] = scale * d_m;
-      d[1] = scale * d_sxx;
-      d[2] = scale * d_sxy;
+      d[n_pixels] = scale * d_sxx;
+      d[2 * size_t(n_pixels)] = scale * d_sxy;
       s_sum += S;
-      l1_sum += fabsf(image[3 * pix + ch] - target[3 * pix + ch]);
+      const int e = (tid / kSsimTile + kSsimR) * kSsimP + tid % kSsimTile + kSsimR;
+      l1_sum += fabsf(s_px[0][e][ch] - s_px[1][e][ch]);
     }
   }
   // tile sums of S and |x - y|
@@ -165,9 +207,9 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(
 __global__ void __launch_bounds__(256) ssim_bwd_kernel(
     const SsimView* __restrict__ views, int n_views, const float* __restrict__ image,
     const float* __restrict__ target, SsimTaps taps, float l1_weight,
-    const float* __restrict__ dstat, float* __restrict__ d_image) {
+    const float* __restrict__ dstat, uint32_t n_pixels, float* __restrict__ d_image) {
   __shared__ float s_in[3][kSsimP][kSsimP];      // d/dm, d/dsxx, d/dsxy
-  __shared__ float s_tmp[3][kSsimP][kSsimTile];
+  __shared__ float s_tmp[3][kSsimP][kSsimTmpW];
   const uint32_t tile = blockIdx.x;
   const SsimView& V = views[ssim_view_of_tile(views, n_views, tile)];
   const int lt = int(tile - V.tile_base);
@@ -184,10 +226,10 @@ __global__ void __launch_bounds__(256) ssim_bwd_kernel(
       const int gx = x0 + c, gy = y0 + r;
       float a = 0.0f, b = 0.0f, d = 0.0f;
       if (gx >= 0 && gx < V.W && gy >= 0 && gy < V.H) {
-        const float* q = dstat + 9 * (size_t(V.pix_base) + size_t(gy) * V.W + gx) + 3 * ch;
+        const float* q = dstat + size_t(3 * ch) * n_pixels + size_t(V.pix_base) + size_t(gy) * V.W + gx;
         a = q[0];
-        b = q[1];
-        d = q[2];
+        b = q[n_pixels];
+        d = q[2 * size_t(n_pixels)];
       }
       s_in[0][r][c] = a;
       s_in[1][r][c] = b;
@@ -298,9 +340,9 @@ extern "C" ubs_status ubs_ssim_loss(int32_t n_views, const int32_t* sizes, const
     const float scale = float(-double(lambda_ssim) / n_entries);
     const float l1_weight = float((1.0 - double(lambda_ssim)) / n_entries);
     hipLaunchKernelGGL(ssim_fwd_kernel, dim3(unsigned(tiles)), dim3(256), 0, st, dviews, n_views,
-                       image, target, taps, scale, dstat, sums);
+                       image, target, taps, scale, dstat, uint32_t(pixels), sums);
     hipLaunchKernelGGL(ssim_bwd_kernel, dim3(unsigned(tiles)), dim3(256), 0, st, dviews, n_views,
-                       image, target, taps, l1_weight, dstat, d_image);
+                       image, target, taps, l1_weight, dstat, uint32_t(pixels), d_image);
   }
   if (loss && tiles > 0)
     hipLaunchKernelGGL(ssim_loss_kernel, dim3(1), dim3(256), 0, st, sums, uint32_t(tiles),
