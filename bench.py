@@ -110,9 +110,10 @@ def stage_bytes(stage: str, c: dict) -> float:
     P, F, R, Pv, K, A, G = c["P"], c["F"], c["R"], c["Pv"], c["K"], c["A"], c["G"]
     return {
         "preprocess": 4.0 * F * P + 48.0 * R,
-        "bin_count": 36.0 * R + 4.0 * K + 4.0 * G,
+        "bin_count": 36.0 * R + 12.0 * K + 4.0 * G,
         "scan": 12.0 * G,
-        "bin_emit": 36.0 * R + 12.0 * K,
+        # the emitting pass runs only when a tile outgrew its slot block
+        "bin_emit": (36.0 * R + 12.0 * K) * c.get("spill", 1),
         "sort": 20.0 * K + 16.0 * G,
         "raster_fwd": 52.0 * K + 20.0 * A + 8.0 * G,
         "grad_clear": 40.0 * R,
@@ -292,7 +293,7 @@ def run_single(args, name, desc):
     assert not st["overflow"] and not st["sort_stalled"], st
     lay = r.layout
     c = {"P": sc.n, "F": int(sc.params.shape[0]), "R": lay.n_records, "Pv": st["n_visible"],
-         "K": st["pairs_needed"], "A": lay.n_pixels, "G": lay.n_tiles}
+         "K": st["pairs_needed"], "A": lay.n_pixels, "G": lay.n_tiles, "spill": st["spill"]}
     dom = max(stages_ms, key=stages_ms.get)
     ach = stage_bytes(dom, c) / (stages_ms[dom] * 1e-3) / 1e9
     frame_bytes = sum(stage_bytes(s, c) for s in stages_ms)

@@ -229,7 +229,10 @@ typedef struct {
   uint32_t n_nonfinite;      /* primitives with non-finite parameters (culled) */
   uint32_t n_visible;        /* records that survived culling */
   uint32_t sort_stalled;     /* reserved, always 0 */
-  uint32_t _pad[10];
+  uint32_t _reserved[3];     /* internal work counters */
+  uint32_t spill;            /* 1 if some tile met more than 256 records: the
+                                frame took the second, emitting binning pass */
+  uint32_t _pad[6];
 } ubs_status_block;
 
 /*
@@ -258,9 +261,12 @@ ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
  * rho (1 + 2^-10), evaluated in float64 without contraction.  Keys are
  * sorted ascending; equal keys keep record-index order (the result is that
  * of a stable sort of the keys emitted record by record).  The pairs are
- * counted per tile, placed in per-tile segments and each segment sorted by
- * (depth, record); tuning.digit_bits sets the digit width of the radix sort
- * used for segments longer than 4096 pairs.
+ * counted per tile and, in the same pass, stored in a block of 256 slots per
+ * tile (part of the workspace); when some tile has more pairs (the status
+ * block's spill flag), a second pass over the records places every pair in
+ * its tile's segment instead.  Each tile's pairs are then sorted by (depth,
+ * record); tuning.digit_bits sets the digit width of the radix sort used for
+ * tiles with more than 4096 pairs.
  */
 ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, void* stream);
 

@@ -71,7 +71,8 @@ class UbsLayout(ctypes.Structure):
 
 class UbsStatusBlock(ctypes.Structure):
     _fields_ = [("pairs_needed", c_uint64), ("overflow", c_uint32), ("n_nonfinite", c_uint32),
-                ("n_visible", c_uint32), ("sort_stalled", c_uint32), ("_pad", c_uint32 * 10)]
+                ("n_visible", c_uint32), ("sort_stalled", c_uint32),
+                ("_reserved", c_uint32 * 3), ("spill", c_uint32), ("_pad", c_uint32 * 6)]
 
 
 class UbsAdam(ctypes.Structure):

@@ -24,17 +24,19 @@ hipError_t launch_scan_compact(const uint32_t* flags, uint32_t n, uint32_t* tile
                                unsigned long long* total_out);
 hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
                             uint32_t n_records, uint32_t* tile_counts, uint32_t* hit_mask,
-                            uint32_t* big_list, uint32_t* big_count, hipStream_t st);
+                            uint32_t* big_list, uint32_t* big_count, unsigned long long* slots,
+                            DevStatus* status, hipStream_t st);
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
                        DevStatus* status, unsigned long long capacity, hipStream_t st,
                        unsigned long long* total_out);
 hipError_t launch_bin_emit(const float* records, const DevView* views, int n_views,
                            uint32_t n_records, const uint32_t* hit_mask, const uint32_t* big_list,
                            const uint32_t* big_count, uint32_t* tile_cursor,
-                           const DevStatus* status, unsigned long long* comp, hipStream_t st);
+                           DevStatus* status, unsigned long long* comp, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
-hipError_t launch_tile_sort(unsigned long long* comp, const uint32_t* tile_counts,
-                            const uint32_t* tile_end, const DevStatus* status,
+hipError_t launch_tile_sort(unsigned long long* comp, const unsigned long long* slots,
+                            const uint32_t* tile_counts, const uint32_t* tile_cursor,
+                            const DevStatus* status,
                             unsigned long long* keys_out, uint32_t* vals_out, uint32_t* ranges,
                             uint32_t n_tiles, int digit_bits, int rec_bits, uint32_t* big_tiles,
                             uint32_t* n_big_tiles, hipStream_t st);
@@ -213,6 +215,7 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.off_blocksums = take(4 * uint64_t(l.n_scan_blocks + 1));
   l.off_keys0 = take(8 * cap);
   l.off_comp = take(8 * cap);
+  l.off_slots = take(8 * uint64_t(kTileSlots) * n_tiles);
   l.off_values0 = take(4 * cap);
   l.pub.off_ranges = take(8 * n_tiles);
   l.pub.off_ncontrib = take(4 * n_pix);
@@ -356,8 +359,9 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
   UBS_HIP(launch_bin_prepare(tile_counts, size_t(n_tiles) + 2, at<uint32_t>(ws, L.off_pre_partials),
                              pre_partials_used(p), uint32_t(L.n_pre_partials), status, s));
   uint32_t* hit_mask = at<uint32_t>(ws, L.off_hit_mask);
+  auto* slots = at<unsigned long long>(ws, L.off_slots);
   UBS_HIP(launch_bin_count(records, views, frame->n_views, n_rec, tile_counts, hit_mask, big_list,
-                           big_count, s));
+                           big_count, slots, status, s));
   stage_mark(frame, UBS_STAGE_BIN_COUNT, 1, s);
   stage_mark(frame, UBS_STAGE_SCAN, 0, s);
   // segment starts of the tiles; the total sets pairs_needed and overflow
@@ -368,7 +372,7 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
                           tile_cursor, status, comp, s));
   stage_mark(frame, UBS_STAGE_BIN_EMIT, 1, s);
   stage_mark(frame, UBS_STAGE_SORT, 0, s);
-  UBS_HIP(launch_tile_sort(comp, tile_counts, tile_cursor, status,
+  UBS_HIP(launch_tile_sort(comp, slots, tile_counts, tile_cursor, status,
                            at<unsigned long long>(ws, L.pub.off_keys),
                            at<uint32_t>(ws, L.pub.off_values), at<uint32_t>(ws, L.pub.off_ranges),
                            n_tiles, L.digit_bits, L.rec_bits, at<uint32_t>(ws, L.off_big_tiles),

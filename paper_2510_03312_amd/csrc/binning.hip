@@ -1,7 +1,8 @@
-// Tile binning: per-tile pair counts, and emission of every (tile, record)
-// pair into its tile's segment (the segments come from an exclusive scan of
-// the counts; the order inside a segment is fixed afterwards by
-// tile_sort.hip).
+// Tile binning: per-tile pair counts, with every (tile, record) key stored
+// in the tile's fixed block of slots in the same pass; for a frame where some
+// tile outgrows its block, a second pass emits every pair into its tile's
+// segment (the segments come from an exclusive scan of the counts).  The
+// order inside a tile is fixed afterwards by tile_sort.hip.
 //
 // A record overlaps a tile iff the minimum of its quadratic form
 // r(p) = a dx^2 + 2 b dx dy + c dy^2 over the rectangle spanned by the
@@ -213,15 +214,31 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
 // record has candidates.  The hits of each record (bit k: candidate k) are
 // kept as a mask for the emission.  Larger records are appended to
 // big_list and binned by bin_big_kernel, a workgroup per record.
+// Counts one pair of `tile` and stores its key in the tile's slot block
+// while the block has room; the first pair beyond it raises the spill flag.
+__device__ __forceinline__ void store_slot(uint32_t tile, unsigned long long key,
+                                           uint32_t* __restrict__ tile_counts,
+                                           unsigned long long* __restrict__ slots,
+                                           DevStatus* __restrict__ status) {
+  const uint32_t slot = atomicAdd(&tile_counts[tile], 1u);
+  if (slot < kTileSlots)
+    slots[size_t(tile) * kTileSlots + slot] = key;
+  else if (slot == kTileSlots)
+    status->spill = 1u;
+}
+
 __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict__ records,
                                                         const DevView* __restrict__ views,
                                                         int n_views, uint32_t n_records,
                                                         uint32_t* __restrict__ tile_counts,
                                                         uint32_t* __restrict__ hit_mask,
                                                         uint32_t* __restrict__ big_list,
-                                                        uint32_t* __restrict__ big_count) {
+                                                        uint32_t* __restrict__ big_count,
+                                                        unsigned long long* __restrict__ slots,
+                                                        DevStatus* __restrict__ status) {
   __shared__ uint32_t s_list[kBinWaves][kBinRecPerWave];
   __shared__ uint32_t s_excl[kBinWaves][65];
+  __shared__ unsigned long long s_key[kBinWaves][64];
   __shared__ float4 s_r0[kBinWaves][64];
   __shared__ float2 s_r1[kBinWaves][64];
   __shared__ int4 s_box[kBinWaves][64];     // tx0, ty0, box width, view
@@ -240,6 +257,7 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict_
     const uint32_t total = uint32_t(__shfl(int(incl), 63, 64));
     s_excl[w][lane] = incl - nc;
     if (lane == 0) s_excl[w][64] = 0xffffffffu;
+    s_key[w][lane] = ((unsigned long long)__float_as_uint(b.depth) << 32) | rec;
     s_r0[w][lane] = b.r0;
     s_r1[w][lane] = make_float2(b.r1.x, b.r1.y);
     s_box[w][lane] = make_int4(b.box.tx0, b.box.ty0, b.box.tx1 - b.box.tx0 + 1, b.view);
@@ -253,7 +271,7 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict_
       const int tx = bx.x + k % bx.z, ty = bx.y + k / bx.z;
       const float2 r1 = s_r1[w][j];
       if (record_hits_tile(s_r0[w][j], make_float4(r1.x, r1.y, 0.f, 0.f), V, tx, ty)) {
-        atomicAdd(&tile_counts[global_tile(V, tx, ty)], 1u);
+        store_slot(global_tile(V, tx, ty), s_key[w][j], tile_counts, slots, status);
         atomicOr(&s_mask[w][j], 1u << k);
       }
     }
@@ -271,19 +289,75 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict_
   }
 }
 
-// Appends (depth bits << 32 | record) of every pair of the records with at
-// most kSmallBox candidates to its tile's segment, replaying bin_count's hit
-// masks as one flat list of hits per 64 records (one round of independent
-// cursor atomics per 64 hits); tile_cursor starts at each segment's first
-// slot and ends one past its last.
+// Records with more than kSmallBox candidate tiles: a workgroup per record
+// (grid-stride over big_list), its threads testing consecutive candidates.
+// EMIT = false counts the hits into tile_counts and stores them in the slot
+// blocks, EMIT = true appends them to the tile segments (spill fallback).
+// Workgroup `block` of `n_blocks` takes records block, block + n_blocks, ...
+template <bool EMIT>
+__device__ __forceinline__ void bin_big_records(uint32_t block, uint32_t n_blocks,
+                                                const float* __restrict__ records,
+                                                const DevView* __restrict__ views, int n_views,
+                                                const uint32_t* __restrict__ big_list,
+                                                const uint32_t* __restrict__ big_count,
+                                                uint32_t* __restrict__ tile_counts,
+                                                uint32_t* __restrict__ tile_cursor,
+                                                DevStatus* __restrict__ status,
+                                                unsigned long long* __restrict__ comp) {
+  const uint32_t nb = *big_count;
+  for (uint32_t bi = block; bi < nb; bi += n_blocks) {
+    const uint32_t rec = big_list[bi];
+    const BinRec o = load_bin_rec(records, views, n_views, rec, true);
+    const DevView& V = views[o.view];
+    const int bw = o.box.tx1 - o.box.tx0 + 1;
+    const unsigned long long key = ((unsigned long long)__float_as_uint(o.depth) << 32) | rec;
+    for (int k = int(threadIdx.x); k < o.n_cand; k += 256) {
+      const int tx = o.box.tx0 + k % bw, ty = o.box.ty0 + k / bw;
+      if (record_hits_tile(o.r0, o.r1, V, tx, ty)) {
+        if (EMIT)
+          comp[atomicAdd(&tile_cursor[global_tile(V, tx, ty)], 1u)] = key;
+        else
+          store_slot(global_tile(V, tx, ty), key, tile_counts, comp, status);
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) bin_big_count_kernel(const float* __restrict__ records,
+                                                            const DevView* __restrict__ views,
+                                                            int n_views,
+                                                            const uint32_t* __restrict__ big_list,
+                                                            const uint32_t* __restrict__ big_count,
+                                                            uint32_t* __restrict__ tile_counts,
+                                                            DevStatus* __restrict__ status,
+                                                            unsigned long long* __restrict__ slots) {
+  bin_big_records<false>(blockIdx.x, gridDim.x, records, views, n_views, big_list, big_count,
+                         tile_counts, nullptr, status, slots);
+}
+
+// Spill pass: appends (depth bits << 32 | record) of every pair to its
+// tile's segment.  The first n_small_blocks workgroups replay bin_count's hit
+// masks of the records with at most kSmallBox candidates as one flat list of
+// hits per 64 records (one round of independent cursor atomics per 64 hits);
+// the others test the big records' candidates again.  tile_cursor starts at
+// each segment's first slot and ends one past its last.  Without a spill
+// every workgroup returns at once.
 __global__ void __launch_bounds__(256) bin_emit_kernel(const float* __restrict__ records,
                                                        const DevView* __restrict__ views,
                                                        int n_views, uint32_t n_records,
                                                        const uint32_t* __restrict__ hit_mask,
+                                                       const uint32_t* __restrict__ big_list,
+                                                       const uint32_t* __restrict__ big_count,
+                                                       uint32_t n_small_blocks,
                                                        uint32_t* __restrict__ tile_cursor,
-                                                       const DevStatus* __restrict__ status,
+                                                       DevStatus* __restrict__ status,
                                                        unsigned long long* __restrict__ comp) {
-  if (status->overflow) return;
+  if (status->overflow || !status->spill) return;
+  if (blockIdx.x >= n_small_blocks) {
+    bin_big_records<true>(blockIdx.x - n_small_blocks, gridDim.x - n_small_blocks, records, views,
+                          n_views, big_list, big_count, nullptr, tile_cursor, status, comp);
+    return;
+  }
   __shared__ uint32_t s_list[kBinWaves][kBinRecPerWave];
   __shared__ uint32_t s_excl[kBinWaves][65];
   __shared__ unsigned long long s_key[kBinWaves][64];
@@ -322,38 +396,6 @@ __global__ void __launch_bounds__(256) bin_emit_kernel(const float* __restrict__
   }
 }
 
-// Records with more than kSmallBox candidate tiles: a workgroup per record
-// (grid-stride over big_list), its threads testing consecutive candidates.
-// EMIT = false counts the hits into tile_counts, EMIT = true appends them.
-template <bool EMIT>
-__global__ void __launch_bounds__(256) bin_big_kernel(const float* __restrict__ records,
-                                                      const DevView* __restrict__ views,
-                                                      int n_views,
-                                                      const uint32_t* __restrict__ big_list,
-                                                      const uint32_t* __restrict__ big_count,
-                                                      uint32_t* __restrict__ tile_counts,
-                                                      uint32_t* __restrict__ tile_cursor,
-                                                      const DevStatus* __restrict__ status,
-                                                      unsigned long long* __restrict__ comp) {
-  if (EMIT && status->overflow) return;
-  const uint32_t nb = *big_count;
-  for (uint32_t bi = blockIdx.x; bi < nb; bi += gridDim.x) {
-    const uint32_t rec = big_list[bi];
-    const BinRec o = load_bin_rec(records, views, n_views, rec, true);
-    const DevView& V = views[o.view];
-    const int bw = o.box.tx1 - o.box.tx0 + 1;
-    const unsigned long long key = ((unsigned long long)__float_as_uint(o.depth) << 32) | rec;
-    for (int k = int(threadIdx.x); k < o.n_cand; k += 256) {
-      const int tx = o.box.tx0 + k % bw, ty = o.box.ty0 + k / bw;
-      if (record_hits_tile(o.r0, o.r1, V, tx, ty)) {
-        if (EMIT)
-          comp[atomicAdd(&tile_cursor[global_tile(V, tx, ty)], 1u)] = key;
-        else
-          atomicAdd(&tile_counts[global_tile(V, tx, ty)], 1u);
-      }
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Exclusive scan of uint32 counts (three phases: tile sums, scan of the tile
@@ -477,12 +519,14 @@ constexpr unsigned kBigBlocks = 1024;
 // tile_counts and *big_count must be zero.
 hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
                             uint32_t n_records, uint32_t* tile_counts, uint32_t* hit_mask,
-                            uint32_t* big_list, uint32_t* big_count, hipStream_t st) {
+                            uint32_t* big_list, uint32_t* big_count, unsigned long long* slots,
+                            DevStatus* status, hipStream_t st) {
   if (n_records == 0) return hipSuccess;
   hipLaunchKernelGGL(bin_count_kernel, dim3(bin_blocks(n_records)), dim3(256), 0, st, records,
-                     views, n_views, n_records, tile_counts, hit_mask, big_list, big_count);
-  hipLaunchKernelGGL(bin_big_kernel<false>, dim3(kBigBlocks), dim3(256), 0, st, records, views,
-                     n_views, big_list, big_count, tile_counts, nullptr, nullptr, nullptr);
+                     views, n_views, n_records, tile_counts, hit_mask, big_list, big_count, slots,
+                     status);
+  hipLaunchKernelGGL(bin_big_count_kernel, dim3(kBigBlocks), dim3(256), 0, st, records, views,
+                     n_views, big_list, big_count, tile_counts, status, slots);
   return hipGetLastError();
 }
 
@@ -594,12 +638,12 @@ hipError_t launch_scan_compact(const uint32_t* flags, uint32_t n, uint32_t* tile
 hipError_t launch_bin_emit(const float* records, const DevView* views, int n_views,
                            uint32_t n_records, const uint32_t* hit_mask, const uint32_t* big_list,
                            const uint32_t* big_count, uint32_t* tile_cursor,
-                           const DevStatus* status, unsigned long long* comp, hipStream_t st) {
+                           DevStatus* status, unsigned long long* comp, hipStream_t st) {
   if (n_records == 0) return hipSuccess;
-  hipLaunchKernelGGL(bin_emit_kernel, dim3(bin_blocks(n_records)), dim3(256), 0, st, records,
-                     views, n_views, n_records, hit_mask, tile_cursor, status, comp);
-  hipLaunchKernelGGL(bin_big_kernel<true>, dim3(kBigBlocks), dim3(256), 0, st, records, views,
-                     n_views, big_list, big_count, nullptr, tile_cursor, status, comp);
+  const unsigned small_blocks = bin_blocks(n_records);
+  hipLaunchKernelGGL(bin_emit_kernel, dim3(small_blocks + kBigBlocks), dim3(256), 0, st, records,
+                     views, n_views, n_records, hit_mask, big_list, big_count, small_blocks,
+                     tile_cursor, status, comp);
   return hipGetLastError();
 }
 
@@ -618,6 +662,7 @@ __global__ void __launch_bounds__(256) bin_prepare_kernel(uint32_t* __restrict__
   if (blockIdx.x != 0) return;
   __shared__ uint32_t s_sum[2][4];
   uint32_t vis = 0, nf = 0;
+#pragma unroll 8
   for (uint32_t k = threadIdx.x; k < n_partials; k += 256) {
     vis += partial[k];
     nf += partial[stride + k];
@@ -633,6 +678,7 @@ __global__ void __launch_bounds__(256) bin_prepare_kernel(uint32_t* __restrict__
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    status->spill = 0u;
     status->n_visible = s_sum[0][0] + s_sum[0][1] + s_sum[0][2] + s_sum[0][3];
     status->n_nonfinite = s_sum[1][0] + s_sum[1][1] + s_sum[1][2] + s_sum[1][3];
   }

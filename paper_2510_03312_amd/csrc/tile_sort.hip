@@ -1,18 +1,21 @@
 // Per-tile ordering of the (tile, record) pairs.
 //
-// Binning counts the pairs of every tile (one atomic per pair), an exclusive
-// scan of those counts gives every tile a contiguous segment, and emission
-// appends the 64-bit key (depth bits << 32 | record) of each pair to its
-// tile's segment through a per-tile cursor, in no particular order.  The
-// key is unique within a tile (a record meets a tile at most once), so
-// sorting each segment by it yields exactly the order of a stable sort of
-// (tile, depth) keys emitted in record order: depth first, equal depths in
-// record order.
+// Binning counts the pairs of every tile (one atomic per pair) and stores
+// the 64-bit key (depth bits << 32 | record) of each in the tile's block of
+// kTileSlots slots, in no particular order; an exclusive scan of the counts
+// gives every tile a contiguous segment of the output.  If some tile has
+// more pairs than slots (the spill flag), a second binning pass appends
+// every key to its tile's segment of `comp` through a per-tile cursor
+// instead, and the sort reads from there.  The key is unique within a tile
+// (a record meets a tile at most once), so sorting a tile's keys yields
+// exactly the order of a stable sort of (tile, depth) keys emitted in record
+// order: depth first, equal depths in record order.
 //
 // tile_sort_small_kernel: one wavefront per tile (grid-stride over tiles);
-//   writes every tile's range and sorts the segments of at most kSmallSort
+//   writes every tile's range and sorts the tiles of at most kSmallSort
 //   pairs by rank (each key's position is the number of smaller keys in the
-//   segment, LDS broadcast reads); larger tiles go to a list for
+//   tile, LDS broadcast reads); larger tiles (spilled frames only) go to a
+//   list for
 // tile_sort_kernel: one workgroup per listed tile.
 //   n <= kLdsSortMax  bitonic sort in LDS, padded to a power of two;
 //   larger            LSD radix sort of the segment in global memory by the
@@ -31,6 +34,7 @@ constexpr int kTileSortThreads = 256;
 constexpr int kLdsSortMax = 4096;   // keys held in LDS (32 KiB)
 constexpr uint32_t kSmallSort = 256;
 static_assert(kSmallSort == 256, "the rank sort counts for up to four 64-key slots");
+static_assert(kTileSlots == kSmallSort, "a tile sorted by a workgroup implies a spilled frame");
 
 __device__ __forceinline__ void write_sorted(unsigned long long key, uint32_t tile, size_t pos,
                                              unsigned long long* __restrict__ keys_out,
@@ -133,19 +137,22 @@ __device__ __forceinline__ void count_smaller(const unsigned long long* s_keys, 
 }
 
 __global__ void __launch_bounds__(64) tile_sort_small_kernel(
-    const unsigned long long* __restrict__ comp, const uint32_t* __restrict__ tile_counts,
-    const uint32_t* __restrict__ tile_end, const DevStatus* __restrict__ status,
-    unsigned long long* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-    uint32_t* __restrict__ ranges, uint32_t n_tiles, uint32_t* __restrict__ big_tiles,
-    uint32_t* __restrict__ n_big_tiles) {
+    const unsigned long long* __restrict__ comp, const unsigned long long* __restrict__ slots,
+    const uint32_t* __restrict__ tile_counts, const uint32_t* __restrict__ tile_cursor,
+    const DevStatus* __restrict__ status, unsigned long long* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out, uint32_t* __restrict__ ranges, uint32_t n_tiles,
+    uint32_t* __restrict__ big_tiles, uint32_t* __restrict__ n_big_tiles) {
   __shared__ unsigned long long s_keys[kSmallSort];
   constexpr int Q = int(kSmallSort / 64);
   const uint32_t lane = threadIdx.x;
   const bool overflow = status->overflow != 0u;
+  const bool spill = status->spill != 0u;
   for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const uint32_t n = overflow ? 0u : tile_counts[t];
-    const uint32_t end = n ? tile_end[t] : 0u;
-    const uint32_t start = end - n;   // an empty tile's range is (0, 0)
+    // the cursor is the segment start, or its end once the spill pass ran
+    const uint32_t start = n ? (spill ? tile_cursor[t] - n : tile_cursor[t]) : 0u;
+    const uint32_t end = start + n;   // an empty tile's range is (0, 0)
+    const unsigned long long* src = spill ? comp + start : slots + size_t(t) * kTileSlots;
     if (lane == 0) {
       ranges[2 * size_t(t)] = start;
       ranges[2 * size_t(t) + 1] = end;
@@ -160,7 +167,7 @@ __global__ void __launch_bounds__(64) tile_sort_small_kernel(
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const uint32_t i = lane + 64u * uint32_t(q);
-      k[q] = i < n ? comp[start + i] : ~0ull;
+      k[q] = i < n ? src[i] : ~0ull;
       if (i < n) s_keys[i] = k[q];
       rank[q] = 0u;
     }
@@ -233,19 +240,20 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_sort_kernel(
 }
 
 // big_tiles: n_tiles words; n_big_tiles must be zero.
-hipError_t launch_tile_sort(unsigned long long* comp, const uint32_t* tile_counts,
-                            const uint32_t* tile_end, const DevStatus* status,
-                            unsigned long long* keys_out, uint32_t* vals_out, uint32_t* ranges,
-                            uint32_t n_tiles, int digit_bits, int rec_bits, uint32_t* big_tiles,
+hipError_t launch_tile_sort(unsigned long long* comp, const unsigned long long* slots,
+                            const uint32_t* tile_counts, const uint32_t* tile_cursor,
+                            const DevStatus* status, unsigned long long* keys_out,
+                            uint32_t* vals_out, uint32_t* ranges, uint32_t n_tiles,
+                            int digit_bits, int rec_bits, uint32_t* big_tiles,
                             uint32_t* n_big_tiles, hipStream_t st) {
   if (n_tiles == 0) return hipSuccess;
   const uint32_t grid = n_tiles < 65536u ? n_tiles : 65536u;
-  hipLaunchKernelGGL(tile_sort_small_kernel, dim3(grid), dim3(64), 0, st, comp, tile_counts,
-                     tile_end, status, keys_out, vals_out, ranges, n_tiles, big_tiles,
-                     n_big_tiles);
+  hipLaunchKernelGGL(tile_sort_small_kernel, dim3(grid), dim3(64), 0, st, comp, slots,
+                     tile_counts, tile_cursor, status, keys_out, vals_out, ranges, n_tiles,
+                     big_tiles, n_big_tiles);
   const uint32_t big_grid = n_tiles < 256u ? n_tiles : 256u;
   hipLaunchKernelGGL(tile_sort_kernel, dim3(big_grid), dim3(kTileSortThreads), 0, st, comp,
-                     tile_counts, tile_end, big_tiles, n_big_tiles, keys_out, vals_out,
+                     tile_counts, tile_cursor, big_tiles, n_big_tiles, keys_out, vals_out,
                      digit_bits, rec_bits);
   return hipGetLastError();
 }

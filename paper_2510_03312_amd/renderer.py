@@ -158,7 +158,7 @@ class Renderer:
         st = _lib.UbsStatusBlock.from_buffer_copy(raw)
         return {"pairs_needed": int(st.pairs_needed), "overflow": int(st.overflow),
                 "n_nonfinite": int(st.n_nonfinite), "n_visible": int(st.n_visible),
-                "sort_stalled": int(st.sort_stalled)}
+                "sort_stalled": int(st.sort_stalled), "spill": int(st.spill)}
 
     def region(self, off: int, count: int, dtype: torch.dtype) -> torch.Tensor:
         esz = torch.tensor([], dtype=dtype).element_size()

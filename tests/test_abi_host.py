@@ -58,7 +58,8 @@ def test_ctypes_structs_match_the_header(tmp_path):
         "ubs_layout": ["bytes", "n_records", "n_tiles", "n_pixels", "pair_capacity", "key_bits",
                        "n_views", "off_status", "off_records", "off_keys", "off_values",
                        "off_ranges", "off_ncontrib", "off_grad2d"],
-        "ubs_status_block": ["pairs_needed", "overflow", "n_nonfinite", "n_visible", "sort_stalled"],
+        "ubs_status_block": ["pairs_needed", "overflow", "n_nonfinite", "n_visible", "sort_stalled",
+                             "spill"],
         "ubs_adam": ["lr_mu_x", "lr_opacity", "lr_scale", "lr_other", "beta1", "beta2", "eps",
                      "lambda_o", "lambda_s", "lambda_eps", "step"],
     }

@@ -113,6 +113,32 @@ def test_bin_sort_bit_exact_multi_view():
     np.testing.assert_array_equal(ranges, rg)
 
 
+@pytest.mark.parametrize("n0,n1", [(256, 255), (256, 257), (257, 1), (0, 256), (1, 0)])
+def test_bin_sort_at_the_tile_slot_capacity(n0, n1):
+    """Two 16x16 tiles holding exactly n0 and n1 pairs: up to 256 pairs a
+    tile the keys come from the counting pass's slot blocks, one more sends
+    the whole frame through the emitting pass."""
+    log(f"[bin_sort] slot capacity {n0}/{n1}")
+    n = n0 + n1
+    cfg = make_config("cfg0", n=n, width=32, height=16)
+    recs = make_splat_records(n, 32, 16, seed=21, cull_frac=0.0, max_extent=1.0)
+    rng = np.random.default_rng(22)
+    # means at least 3 px inside their tile: a record meets its own tile only
+    recs[:, 0] = np.where(np.arange(recs.shape[0]) < n0, rng.uniform(4.0, 12.0, recs.shape[0]),
+                          rng.uniform(20.0, 28.0, recs.shape[0])).astype(np.float32)
+    recs[:, 1] = rng.uniform(4.0, 12.0, recs.shape[0]).astype(np.float32)
+    if recs.shape[0] >= 40:
+        recs[:20, 11] = recs[20:40, 11]      # exact depth ties
+    sk, sv, rg = bin_reference(recs, [_V(cfg["views"][0], recs.shape[0])])
+    assert list((rg[:, 1] - rg[:, 0]).astype(int)) == [n0, n1]
+    r, frame, K, keys, vals, ranges = _inject_and_sort(cfg, recs)
+    assert r.status()["spill"] == int(max(n0, n1) > 256)
+    assert K == sk.size
+    np.testing.assert_array_equal(keys, sk)
+    np.testing.assert_array_equal(vals, sv)
+    np.testing.assert_array_equal(ranges, rg)
+
+
 @pytest.mark.parametrize("digit_bits", [4, 5, 7, 8])
 @pytest.mark.parametrize("n,W,H,ext", [(2000, 300, 200, 30.0),    # short segments: rank sort
                                        (3000, 64, 48, 40.0),      # 395-519 per tile: bitonic
