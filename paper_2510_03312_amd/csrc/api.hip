@@ -10,18 +10,14 @@
 namespace ubs {
 
 hipError_t launch_preprocess_fwd(bool fp64, const DevScene& S, int scene, const DevView* views,
-                                 int n_views, float* records, uint32_t* live, uint32_t* partial,
+                                 int n_views, float* records, LiveOut live, uint32_t* partial,
                                  uint32_t stride, hipStream_t st);
 hipError_t launch_bin_prepare(uint32_t* words, size_t n_words, const uint32_t* partial,
                               uint32_t n_partials, uint32_t stride, DevStatus* status,
                               hipStream_t st);
 hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const DevView* views,
-                                 int n_views, const float* records, float* grad2d,
-                                 const uint32_t* live, const uint32_t* offs, const uint32_t* list,
-                                 const unsigned long long* n_live, float* compact, hipStream_t st);
-hipError_t launch_scan_compact(const uint32_t* flags, uint32_t n, uint32_t* tile_sums,
-                               uint32_t* offsets, uint32_t* list, hipStream_t st,
-                               unsigned long long* total_out);
+                                 int n_views, const float* records, float* grad2d, LiveIn kept,
+                                 float* compact, hipStream_t st);
 hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
                             uint32_t n_records, uint32_t* tile_counts, uint32_t* hit_mask,
                             uint32_t* big_list, uint32_t* big_count, unsigned long long* slots,
@@ -62,11 +58,14 @@ struct ViewChunk {
 };
 
 // Writes a chunk of view descriptors; the first chunk's launch also clears
-// the status block (s != nullptr).
+// the status block (s != nullptr) and the n_scenes kept-primitive counters.
 __global__ void upload_views_kernel(ViewChunk c, DevView* __restrict__ dst,
-                                    DevStatus* __restrict__ s) {
+                                    DevStatus* __restrict__ s, uint32_t* __restrict__ n_kept,
+                                    int n_counters) {
   const int k = threadIdx.x;
   if (k < c.count) dst[c.first + k] = c.v[k];
+  if (s)
+    for (int j = k; j < n_counters; j += int(blockDim.x)) n_kept[j] = 0u;
   if (s && k == 0) {
     s->pairs_needed = 0;
     s->overflow = 0;
@@ -126,7 +125,7 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   if (tu.pair_capacity < 0 || tu.pair_capacity > int64_t(1) << 30) return UBS_ERR_ARG;
   ds->clear();
   dv->clear();
-  uint64_t n_prims = 0, n_grad_compact = 0;
+  uint64_t n_prims = 0, n_grad_compact = 0, n_list = 0;
   for (int s = 0; s < f->n_scenes; ++s) {
     const ubs_scene& S = f->scenes[s];
     if (S.dim < 3 || S.dim > kMaxDim) return UBS_ERR_ARG;
@@ -143,7 +142,9 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
     d.F = param_rows(S.dim - 3, S.rot).F;
     d.variant = tu.flags & (UBS_TUNE_NO_BETA_COND | UBS_TUNE_NO_BETA_OPACITY);
     d.prim_base = int64_t(n_prims);
+    d.list_base = int64_t(n_list);
     n_prims += uint64_t(S.n);
+    n_list += uint64_t(kKeptLists) * kept_list_cap(S.n);
     n_grad_compact = n_grad_compact > uint64_t(d.F) * uint64_t(S.n) ? n_grad_compact
                                                                        : uint64_t(d.F) * uint64_t(S.n);
     if (n_prims > 0x7fffffffull) return UBS_ERR_UNSUPPORTED;
@@ -222,8 +223,8 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.pub.off_grad2d = take(uint64_t(kGradFloats) * 4 * n_rec);
   l.off_tfinal_ws = take(4 * n_pix);
   l.off_live = take(4 * n_prims);
-  l.off_live_list = take(4 * n_prims);
-  l.off_live_count = take(8 * uint64_t(f->n_scenes > 0 ? f->n_scenes : 1));
+  l.off_live_list = take(4 * n_list);
+  l.off_live_count = take(4 * uint64_t(kKeptLists) * uint64_t(f->n_scenes > 0 ? f->n_scenes : 1));
   l.off_grad_compact = take(4 * n_grad_compact);
   // per-workgroup counts of the preprocess launches (one launch per scene)
   l.n_pre_partials = int64_t(n_prims / 256 + uint64_t(f->n_scenes) + 1);
@@ -311,7 +312,8 @@ ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes, u
     c.count = frame->n_views - first < kViewChunk ? frame->n_views - first : kViewChunk;
     for (int k = 0; k < c.count; ++k) c.v[k] = p.dv[first + k];
     hipLaunchKernelGGL(upload_views_kernel, dim3(1), dim3(64), 0, s, c, views,
-                       first == 0 ? status : nullptr);
+                       first == 0 ? status : nullptr,
+                       at<uint32_t>(ws, L.off_live_count), frame->n_scenes * int(kKeptLists));
   }
   UBS_HIP(hipGetLastError());
   const bool fp64 = (frame->tuning.flags & UBS_TUNE_PRE_FP32) == 0;
@@ -324,8 +326,12 @@ ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes, u
     bool used = false;
     for (const DevView& v : p.dv) used = used || v.scene == sc;
     if (!used || p.ds[sc].n == 0) continue;
-    UBS_HIP(launch_preprocess_fwd(fp64, p.ds[sc], sc, views, frame->n_views, records,
-                                  at<uint32_t>(ws, L.off_live) + p.ds[sc].prim_base,
+    const LiveOut kept{at<uint32_t>(ws, L.off_live) + p.ds[sc].prim_base,
+                       at<uint32_t>(ws, L.off_offsets) + p.ds[sc].prim_base,
+                       at<uint32_t>(ws, L.off_live_list) + p.ds[sc].list_base,
+                       at<uint32_t>(ws, L.off_live_count) + size_t(sc) * kKeptLists,
+                       kept_list_cap(p.ds[sc].n)};
+    UBS_HIP(launch_preprocess_fwd(fp64, p.ds[sc], sc, views, frame->n_views, records, kept,
                                   partial + block_base, stride, s));
     block_base += uint32_t((p.ds[sc].n + 255) / 256);
   }
@@ -449,16 +455,16 @@ ubs_status ubs_render_bwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
                          p.ds[sc].dparams, nf);
       continue;
     }
-    // compact the primitives some view kept; the adjoint runs only for those
-    const uint32_t* live = at<uint32_t>(ws, L.off_live) + p.ds[sc].prim_base;
-    uint32_t* list = at<uint32_t>(ws, L.off_live_list) + p.ds[sc].prim_base;
-    unsigned long long* n_live = at<unsigned long long>(ws, L.off_live_count) + sc;
-    uint32_t* offs = at<uint32_t>(ws, L.off_offsets);
-    UBS_HIP(launch_scan_compact(live, uint32_t(p.ds[sc].n), at<uint32_t>(ws, L.off_blocksums),
-                                offs, list, s, n_live));
+    // the adjoint runs only for the primitives some view kept (listed by
+    // the forward preprocess)
+    const LiveIn kept{at<uint32_t>(ws, L.off_live) + p.ds[sc].prim_base,
+                      at<uint32_t>(ws, L.off_offsets) + p.ds[sc].prim_base,
+                      at<uint32_t>(ws, L.off_live_list) + p.ds[sc].list_base,
+                      at<uint32_t>(ws, L.off_live_count) + size_t(sc) * kKeptLists,
+                      kept_list_cap(p.ds[sc].n)};
     UBS_HIP(launch_preprocess_bwd(fp64, p.ds[sc], sc, views, frame->n_views,
-                                  at<float>(ws, L.pub.off_records), grad2d, live, offs, list,
-                                  n_live, at<float>(ws, L.off_grad_compact), s));
+                                  at<float>(ws, L.pub.off_records), grad2d, kept,
+                                  at<float>(ws, L.off_grad_compact), s));
   }
   stage_mark(frame, UBS_STAGE_PRE_BWD, 1, s);
   UBS_HIP(hipGetLastError());

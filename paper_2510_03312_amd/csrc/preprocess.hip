@@ -12,7 +12,7 @@ template <typename T, int C, int ROT>
 __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int scene,
                                                              const DevView* __restrict__ views,
                                                              int n_views, float* __restrict__ records,
-                                                             uint32_t* __restrict__ live,
+                                                             LiveOut kept,
                                                              uint32_t* __restrict__ partial,
                                                              uint32_t partial_stride) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
@@ -57,25 +57,52 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
     store_stream(&rp[1], o1);
     store_stream(&rp[2], o2);
   }
-  if (active) live[i] = visible > 0 ? 1u : 0u;
-  // per-workgroup counts (no atomics on a shared word: those serialise across
-  // the chip); the binning's first kernel adds them into the status block
+  const bool keep = active && visible > 0;
+  if (active) kept.flags[i] = keep ? 1u : 0u;
+  // per-workgroup counts (no atomics on a shared word per wavefront: those
+  // serialise across the chip); the binning's first kernel adds them into
+  // the status block.  The kept primitives go to the adjoint's list: one
+  // atomic per workgroup reserves their run (ascending inside it), and only
+  // the first wavefront waits for it, the others end here.
   __shared__ uint32_t s_cnt[2];
+  __shared__ unsigned long long s_keep[4];
   if (threadIdx.x == 0) { s_cnt[0] = 0; s_cnt[1] = 0; }
   __syncthreads();
   const unsigned long long nf = __ballot(active && !finite);
-  const int lane = threadIdx.x & 63;
+  const unsigned long long km = __ballot(keep);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t vis = visible;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) vis += __shfl_xor(vis, o, 64);
   if (lane == 0) {
     if (nf) atomicAdd(&s_cnt[0], uint32_t(__popcll(nf)));
     if (vis) atomicAdd(&s_cnt[1], vis);
+    s_keep[wave] = km;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (wave != 0) return;
+  const unsigned long long m0 = s_keep[0], m1 = s_keep[1], m2 = s_keep[2], m3 = s_keep[3];
+  const uint32_t n_keep = uint32_t(__popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3));
+  const uint32_t which = blockIdx.x % kKeptLists;
+  uint32_t base = 0;
+  if (lane == 0) {
     partial[blockIdx.x] = s_cnt[1];
     partial[partial_stride + blockIdx.x] = s_cnt[0];
+    if (n_keep) base = atomicAdd(&kept.count[which], n_keep);
+  }
+  base = uint32_t(__shfl(int(base), 0, 64));
+  uint32_t* list = kept.list + size_t(which) * kept.cap;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const int64_t i0 = int64_t(blockIdx.x) * 256 + lane;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const unsigned long long m = w == 0 ? m0 : (w == 1 ? m1 : (w == 2 ? m2 : m3));
+    if ((m >> lane) & 1ull) {
+      const uint32_t p = base + uint32_t(__popcll(m & lt));
+      list[p] = uint32_t(i0 + 64 * w);
+      kept.pos[i0 + 64 * w] = p;
+    }
+    base += uint32_t(__popcll(m));
   }
 }
 
@@ -104,21 +131,31 @@ __device__ __forceinline__ void record_gradient_from_sums(const float* __restric
   g[6] = g[6] * 0.69314718f;
 }
 
-// Thread t runs the adjoint of the t-th live primitive of the compacted list
-// and writes its gradient to column t of the compacted [F][n] buffer
-// (coalesced); scatter_dparams_kernel moves it to the primitive's column.
+// Thread t runs the adjoint of the t-th kept primitive (in the concatenation
+// of the kept lists) and writes its gradient to column t of the compacted
+// [F][n] buffer (coalesced); scatter_dparams_kernel moves it to the
+// primitive's column.
 template <typename T, int C, int ROT>
 __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int scene,
                                                              const DevView* __restrict__ views,
                                                              int n_views,
                                                              const float* __restrict__ records,
                                                              float* __restrict__ grad2d,
-                                                             const uint32_t* __restrict__ list,
-                                                             const unsigned long long* __restrict__ n_live,
+                                                             LiveIn kept,
                                                              float* __restrict__ compact) {
   const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (t >= int64_t(*n_live)) return;
-  const int64_t i = list[t];
+  uint32_t total;
+  const uint32_t excl = kept_list_prefix(kept.count, &total);
+  // the list holding entry t: the last k with excl(k) <= t (binary search
+  // over the lanes' prefixes, every lane active)
+  const uint32_t tt = t < int64_t(total) ? uint32_t(t) : 0u;
+  int lo = 0;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1)
+    if (uint32_t(__shfl(int(excl), lo + step, 64)) <= tt) lo += step;
+  const uint32_t start = uint32_t(__shfl(int(excl), lo, 64));
+  if (t >= int64_t(total)) return;
+  const int64_t i = kept.list[size_t(lo) * kept.cap + (tt - start)];
   Raw<C, ROT> r;
   load_raw<C, ROT>(S.params, S.n, i, r);
   Geo<T, C, ROT> g;
@@ -150,20 +187,23 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int sce
   for (int k = 0; k < F; ++k) compact[int64_t(k) * S.n + t] = out[k];
 }
 
-// dparams[k, i] = compact[k, offs[i]] for live primitives, 0 otherwise.  One
+// dparams[k, i] = compact[k, j(i)] for kept primitives (j: position in the
+// concatenated kept lists), 0 otherwise.  One
 // primitive per thread; the rows go in chunks whose loads are all issued
 // before their stores, so a wavefront waits for memory once per chunk
 // rather than once per row.
 constexpr int kScatterChunk = 9;
 
-__global__ void __launch_bounds__(256) scatter_dparams_kernel(DevScene S,
-                                                              const uint32_t* __restrict__ live,
-                                                              const uint32_t* __restrict__ offs,
+__global__ void __launch_bounds__(256) scatter_dparams_kernel(DevScene S, LiveIn kept,
                                                               const float* __restrict__ compact) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  // the workgroup's 256 primitives are preprocess workgroup blockIdx.x's
+  uint32_t total;
+  const uint32_t excl = kept_list_prefix(kept.count, &total);
+  const uint32_t start = uint32_t(__shfl(int(excl), int(blockIdx.x % kKeptLists), 64));
   if (i >= S.n) return;
-  const bool is_live = live[i] != 0;
-  const int64_t j = is_live ? int64_t(offs[i]) : 0;
+  const bool is_live = kept.flags[i] != 0;
+  const int64_t j = is_live ? int64_t(start) + int64_t(kept.pos[i]) : 0;
   for (int k0 = 0; k0 < S.F; k0 += kScatterChunk) {
     float v[kScatterChunk];
 #pragma unroll
@@ -181,7 +221,7 @@ __global__ void __launch_bounds__(256) scatter_dparams_kernel(DevScene S,
 
 template <typename T, int C, int ROT>
 static hipError_t pre_fwd_t(const DevScene& S, int scene, const DevView* views, int n_views,
-                            float* records, uint32_t* live, uint32_t* partial, uint32_t stride,
+                            float* records, LiveOut live, uint32_t* partial, uint32_t stride,
                             hipStream_t st) {
   const unsigned blocks = unsigned((S.n + 255) / 256);
   hipLaunchKernelGGL((preprocess_fwd_kernel<T, C, ROT>), dim3(blocks), dim3(256), 0, st, S, scene,
@@ -191,20 +231,18 @@ static hipError_t pre_fwd_t(const DevScene& S, int scene, const DevView* views, 
 
 template <typename T, int C, int ROT>
 static hipError_t pre_bwd_t(const DevScene& S, int scene, const DevView* views, int n_views,
-                            const float* records, float* grad2d, const uint32_t* live,
-                            const uint32_t* offs, const uint32_t* list,
-                            const unsigned long long* n_live, float* compact, hipStream_t st) {
+                            const float* records, float* grad2d, LiveIn kept, float* compact,
+                            hipStream_t st) {
   const unsigned blocks = unsigned((S.n + 255) / 256);
   hipLaunchKernelGGL((preprocess_bwd_kernel<T, C, ROT>), dim3(blocks), dim3(256), 0, st, S, scene,
-                     views, n_views, records, grad2d, list, n_live, compact);
-  hipLaunchKernelGGL(scatter_dparams_kernel, dim3(blocks), dim3(256), 0, st, S, live, offs,
-                     compact);
+                     views, n_views, records, grad2d, kept, compact);
+  hipLaunchKernelGGL(scatter_dparams_kernel, dim3(blocks), dim3(256), 0, st, S, kept, compact);
   return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t pre_fwd_dispatch(const DevScene& S, int scene, const DevView* views, int n_views,
-                                   float* records, uint32_t* live, uint32_t* partial,
+                                   float* records, LiveOut live, uint32_t* partial,
                                    uint32_t stride, hipStream_t st) {
   const int C = S.dim - 3;
   if (S.rot == UBS_ROT_QUAT) {
@@ -227,25 +265,23 @@ static hipError_t pre_fwd_dispatch(const DevScene& S, int scene, const DevView* 
 
 template <typename T>
 static hipError_t pre_bwd_dispatch(const DevScene& S, int scene, const DevView* views, int n_views,
-                                   const float* records, float* grad2d, const uint32_t* live,
-                                   const uint32_t* offs, const uint32_t* list,
-                                   const unsigned long long* n_live, float* compact,
-                                   hipStream_t st) {
+                                   const float* records, float* grad2d, LiveIn kept,
+                                   float* compact, hipStream_t st) {
   const int C = S.dim - 3;
   if (S.rot == UBS_ROT_QUAT) {
-    if (C == 0) return pre_bwd_t<T, 0, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
-    if (C == 3) return pre_bwd_t<T, 3, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
-    if (C == 4) return pre_bwd_t<T, 4, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
-    if (C == 5) return pre_bwd_t<T, 5, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
-    if (C == 6) return pre_bwd_t<T, 6, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
-    if (C == 7) return pre_bwd_t<T, 7, 0>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
+    if (C == 0) return pre_bwd_t<T, 0, 0>(S, scene, views, n_views, records, grad2d, kept, compact, st);
+    if (C == 3) return pre_bwd_t<T, 3, 0>(S, scene, views, n_views, records, grad2d, kept, compact, st);
+    if (C == 4) return pre_bwd_t<T, 4, 0>(S, scene, views, n_views, records, grad2d, kept, compact, st);
+    if (C == 5) return pre_bwd_t<T, 5, 0>(S, scene, views, n_views, records, grad2d, kept, compact, st);
+    if (C == 6) return pre_bwd_t<T, 6, 0>(S, scene, views, n_views, records, grad2d, kept, compact, st);
+    if (C == 7) return pre_bwd_t<T, 7, 0>(S, scene, views, n_views, records, grad2d, kept, compact, st);
   } else {
-    if (C == 0) return pre_bwd_t<T, 0, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
-    if (C == 3) return pre_bwd_t<T, 3, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
-    if (C == 4) return pre_bwd_t<T, 4, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
-    if (C == 5) return pre_bwd_t<T, 5, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
-    if (C == 6) return pre_bwd_t<T, 6, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
-    if (C == 7) return pre_bwd_t<T, 7, 1>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
+    if (C == 0) return pre_bwd_t<T, 0, 1>(S, scene, views, n_views, records, grad2d, kept, compact, st);
+    if (C == 3) return pre_bwd_t<T, 3, 1>(S, scene, views, n_views, records, grad2d, kept, compact, st);
+    if (C == 4) return pre_bwd_t<T, 4, 1>(S, scene, views, n_views, records, grad2d, kept, compact, st);
+    if (C == 5) return pre_bwd_t<T, 5, 1>(S, scene, views, n_views, records, grad2d, kept, compact, st);
+    if (C == 6) return pre_bwd_t<T, 6, 1>(S, scene, views, n_views, records, grad2d, kept, compact, st);
+    if (C == 7) return pre_bwd_t<T, 7, 1>(S, scene, views, n_views, records, grad2d, kept, compact, st);
   }
   return hipErrorInvalidValue;
 }
@@ -253,7 +289,7 @@ static hipError_t pre_bwd_dispatch(const DevScene& S, int scene, const DevView* 
 // partial: this launch's slice of the per-workgroup counts (visible records
 // at partial[b], non-finite primitives at partial[stride + b]).
 hipError_t launch_preprocess_fwd(bool fp64, const DevScene& S, int scene, const DevView* views,
-                                 int n_views, float* records, uint32_t* live, uint32_t* partial,
+                                 int n_views, float* records, LiveOut live, uint32_t* partial,
                                  uint32_t stride, hipStream_t st) {
   if (S.n == 0) return hipSuccess;
   return fp64 ? pre_fwd_dispatch<double>(S, scene, views, n_views, records, live, partial, stride, st)
@@ -261,12 +297,11 @@ hipError_t launch_preprocess_fwd(bool fp64, const DevScene& S, int scene, const 
 }
 
 hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const DevView* views,
-                                 int n_views, const float* records, float* grad2d,
-                                 const uint32_t* live, const uint32_t* offs, const uint32_t* list,
-                                 const unsigned long long* n_live, float* compact, hipStream_t st) {
+                                 int n_views, const float* records, float* grad2d, LiveIn kept,
+                                 float* compact, hipStream_t st) {
   if (S.n == 0) return hipSuccess;
-  return fp64 ? pre_bwd_dispatch<double>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st)
-              : pre_bwd_dispatch<float>(S, scene, views, n_views, records, grad2d, live, offs, list, n_live, compact, st);
+  return fp64 ? pre_bwd_dispatch<double>(S, scene, views, n_views, records, grad2d, kept, compact, st)
+              : pre_bwd_dispatch<float>(S, scene, views, n_views, records, grad2d, kept, compact, st);
 }
 
 }  // namespace ubs

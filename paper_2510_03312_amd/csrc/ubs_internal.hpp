@@ -44,6 +44,7 @@ struct DevScene {
   int32_t dim, rot, F;
   uint32_t variant;    // UBS_TUNE_NO_BETA_* bits of the frame (Sec. 5.3 ablations)
   int64_t prim_base;   // first entry of this scene in per-primitive tables
+  int64_t list_base;   // first entry of this scene's kept lists
 };
 
 // Row offsets of the parameter format (component-major [F][n]).
@@ -91,6 +92,51 @@ constexpr int kMaxRows = param_rows(kMaxDim - 3, UBS_ROT_QUAT).F;
 __host__ __device__ constexpr bool dim_ok(int dim) {
   return dim == 3 || (dim >= 6 && dim <= kMaxDim);
 }
+
+// Where the forward preprocess leaves the primitives some view kept, for
+// the adjoint.  The kept primitives of preprocess workgroup b (256
+// primitives) go to list b mod kKeptLists, each list holding up to `cap`
+// entries (cap = kept_list_cap(n)), with `count` entries per list; pos is a
+// kept primitive's index inside its list.  A primitive's position in the
+// concatenation of the lists, which the adjoint's compacted buffer uses, is
+// its pos plus the counts of the lists before its own.  (Several counters
+// spread the workgroups' reserving atomics over several addresses.)
+constexpr uint32_t kKeptLists = 64;
+__host__ __device__ constexpr uint32_t kept_list_cap(int64_t n) {
+  return uint32_t(((n + 255) / 256 + kKeptLists - 1) / kKeptLists) * 256u;
+}
+struct LiveOut {
+  uint32_t* flags;   // per primitive, 1 if kept
+  uint32_t* pos;
+  uint32_t* list;    // kKeptLists lists of cap entries
+  uint32_t* count;   // kKeptLists counters, zeroed before the preprocess launch
+  uint32_t cap;
+};
+struct LiveIn {
+  const uint32_t* flags;
+  const uint32_t* pos;
+  const uint32_t* list;
+  const uint32_t* count;
+  uint32_t cap;
+};
+
+// Within a wavefront: lane k < kKeptLists holds the exclusive prefix of the
+// kept-list counts at k (kKeptLists == 64: one list per lane); also returns
+// the total in *total.
+__device__ __forceinline__ uint32_t kept_list_prefix(const uint32_t* __restrict__ count,
+                                                     uint32_t* total) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t c = count[lane];
+  uint32_t x = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  *total = uint32_t(__shfl(int(x), 63, 64));
+  return x - c;
+}
+static_assert(kKeptLists == 64, "one kept list per lane of a wavefront");
 
 // Status block, mirrors ubs_status_block.
 struct DevStatus {
