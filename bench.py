@@ -362,7 +362,8 @@ def run_batched(args, name, desc):
         st = gf.status()
         assert not st["overflow"] and not st["sort_stalled"], st
         batched[mode] = {"views_per_s": round(len(views) * 1000.0 / ms, 2), "ms_per_frame": round(ms, 4),
-                         "stages_ms": {k: round(v, 4) for k, v in stages.items()}}
+                         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+                         "tile_slots": gf.r.tile_slots or 256, "spill": st["spill"]}
         del gf
         torch.cuda.empty_cache()
         # the same views one per frame through the single-view path

@@ -132,7 +132,10 @@ typedef struct {
  * frame needs more, ubs_bin_sort sets the status overflow flag, emits no
  * pairs and the render calls draw nothing (rerun with a larger capacity,
  * see ubs_status_block.pairs_needed); at most 2^30 pairs.  flags:
- * UBS_TUNE_* bits.
+ * UBS_TUNE_* bits.  tile_slots: 0 (meaning 256) or a multiple of 64 in
+ * [256, 4096], the pairs each tile can hold in the workspace's slot block
+ * (8 bytes each); a frame where some tile has more takes a second binning
+ * pass (same result, slower; ubs_status_block.spill tells).
  */
 #define UBS_TUNE_PERSISTENT 1u  /* raster through a persistent grid that takes
                                    tiles from a work queue (16 wavefronts per CU) */
@@ -148,7 +151,7 @@ typedef struct {
   int32_t digit_bits;
   int64_t pair_capacity;
   uint32_t flags;
-  int32_t _pad;
+  int32_t tile_slots;
 } ubs_tuning;
 
 /*
@@ -230,8 +233,9 @@ typedef struct {
   uint32_t n_visible;        /* records that survived culling */
   uint32_t sort_stalled;     /* reserved, always 0 */
   uint32_t _reserved[3];     /* internal work counters */
-  uint32_t spill;            /* 1 if some tile met more than 256 records: the
-                                frame took the second, emitting binning pass */
+  uint32_t spill;            /* 1 if some tile met more records than
+                                tuning.tile_slots: the frame took the second,
+                                emitting binning pass */
   uint32_t _pad[6];
 } ubs_status_block;
 
@@ -261,10 +265,10 @@ ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
  * rho (1 + 2^-10), evaluated in float64 without contraction.  Keys are
  * sorted ascending; equal keys keep record-index order (the result is that
  * of a stable sort of the keys emitted record by record).  The pairs are
- * counted per tile and, in the same pass, stored in a block of 256 slots per
- * tile (part of the workspace); when some tile has more pairs (the status
- * block's spill flag), a second pass over the records places every pair in
- * its tile's segment instead.  Each tile's pairs are then sorted by (depth,
+ * counted per tile and, in the same pass, stored in a block of
+ * tuning.tile_slots slots per tile (part of the workspace); when some tile
+ * has more pairs (the status block's spill flag), a second pass over the
+ * records places every pair in its tile's segment instead.  Each tile's pairs are then sorted by (depth,
  * record); tuning.digit_bits sets the digit width of the radix sort used for
  * tiles with more than 4096 pairs.
  */

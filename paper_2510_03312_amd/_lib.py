@@ -47,7 +47,7 @@ class UbsView(ctypes.Structure):
 class UbsTuning(ctypes.Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("batch_depth", c_int32),
                 ("digit_bits", c_int32), ("pair_capacity", c_int64), ("flags", c_uint32),
-                ("_pad", c_int32)]
+                ("tile_slots", c_int32)]
 
 
 class UbsFrame(ctypes.Structure):

@@ -42,7 +42,8 @@ def candidates(base: Optional[Tuning] = None) -> List[Tuning]:
         for b in BATCHES:
             for p in PERSISTENT:
                 out.append(Tuning(tile_w=tw, tile_h=th, batch_depth=b, digit_bits=base.digit_bits,
-                                  flags=(base.flags & ~UBS_TUNE_PERSISTENT) | (UBS_TUNE_PERSISTENT if p else 0)))
+                                  flags=(base.flags & ~UBS_TUNE_PERSISTENT) | (UBS_TUNE_PERSISTENT if p else 0),
+                                  tile_slots=base.tile_slots))
     return out
 
 

@@ -21,7 +21,7 @@ hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const 
 hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
                             uint32_t n_records, uint32_t* tile_counts, uint32_t* hit_mask,
                             uint32_t* big_list, uint32_t* big_count, unsigned long long* slots,
-                            DevStatus* status, hipStream_t st);
+                            uint32_t slot_cap, DevStatus* status, hipStream_t st);
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
                        DevStatus* status, unsigned long long capacity, hipStream_t st,
                        unsigned long long* total_out);
@@ -31,8 +31,8 @@ hipError_t launch_bin_emit(const float* records, const DevView* views, int n_vie
                            DevStatus* status, unsigned long long* comp, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_tile_sort(unsigned long long* comp, const unsigned long long* slots,
-                            const uint32_t* tile_counts, const uint32_t* tile_cursor,
-                            const DevStatus* status,
+                            uint32_t slot_cap, const uint32_t* tile_counts,
+                            const uint32_t* tile_cursor, const DevStatus* status,
                             unsigned long long* keys_out, uint32_t* vals_out, uint32_t* ranges,
                             uint32_t n_tiles, int digit_bits, int rec_bits, uint32_t* big_tiles,
                             uint32_t* n_big_tiles, hipStream_t st);
@@ -122,6 +122,9 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   if (!tile_ok(tu.tile_w, tu.tile_h)) return UBS_ERR_UNSUPPORTED;
   if (tu.digit_bits < 4 || tu.digit_bits > 8) return UBS_ERR_UNSUPPORTED;
   if (!batch_ok(tu.batch_depth)) return UBS_ERR_UNSUPPORTED;
+  if (tu.tile_slots != 0 && (tu.tile_slots < int32_t(kDefaultTileSlots) ||
+                             tu.tile_slots > int32_t(kMaxTileSlots) || tu.tile_slots % 64 != 0))
+    return UBS_ERR_UNSUPPORTED;
   if (tu.pair_capacity < 0 || tu.pair_capacity > int64_t(1) << 30) return UBS_ERR_ARG;
   ds->clear();
   dv->clear();
@@ -216,7 +219,8 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.off_blocksums = take(4 * uint64_t(l.n_scan_blocks + 1));
   l.off_keys0 = take(8 * cap);
   l.off_comp = take(8 * cap);
-  l.off_slots = take(8 * uint64_t(kTileSlots) * n_tiles);
+  l.tile_slots = f->tuning.tile_slots ? uint32_t(f->tuning.tile_slots) : kDefaultTileSlots;
+  l.off_slots = take(8 * uint64_t(l.tile_slots) * n_tiles);
   l.off_values0 = take(4 * cap);
   l.pub.off_ranges = take(8 * n_tiles);
   l.pub.off_ncontrib = take(4 * n_pix);
@@ -367,7 +371,7 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
   uint32_t* hit_mask = at<uint32_t>(ws, L.off_hit_mask);
   auto* slots = at<unsigned long long>(ws, L.off_slots);
   UBS_HIP(launch_bin_count(records, views, frame->n_views, n_rec, tile_counts, hit_mask, big_list,
-                           big_count, slots, status, s));
+                           big_count, slots, L.tile_slots, status, s));
   stage_mark(frame, UBS_STAGE_BIN_COUNT, 1, s);
   stage_mark(frame, UBS_STAGE_SCAN, 0, s);
   // segment starts of the tiles; the total sets pairs_needed and overflow
@@ -378,7 +382,7 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
                           tile_cursor, status, comp, s));
   stage_mark(frame, UBS_STAGE_BIN_EMIT, 1, s);
   stage_mark(frame, UBS_STAGE_SORT, 0, s);
-  UBS_HIP(launch_tile_sort(comp, slots, tile_counts, tile_cursor, status,
+  UBS_HIP(launch_tile_sort(comp, slots, L.tile_slots, tile_counts, tile_cursor, status,
                            at<unsigned long long>(ws, L.pub.off_keys),
                            at<uint32_t>(ws, L.pub.off_values), at<uint32_t>(ws, L.pub.off_ranges),
                            n_tiles, L.digit_bits, L.rec_bits, at<uint32_t>(ws, L.off_big_tiles),

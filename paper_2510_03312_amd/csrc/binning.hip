@@ -214,16 +214,17 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
 // record has candidates.  The hits of each record (bit k: candidate k) are
 // kept as a mask for the emission.  Larger records are appended to
 // big_list and binned by bin_big_kernel, a workgroup per record.
-// Counts one pair of `tile` and stores its key in the tile's slot block
-// while the block has room; the first pair beyond it raises the spill flag.
+// Counts one pair of `tile` and stores its key in the tile's block of `cap`
+// slots while the block has room; the first pair beyond it raises the spill
+// flag.
 __device__ __forceinline__ void store_slot(uint32_t tile, unsigned long long key,
                                            uint32_t* __restrict__ tile_counts,
-                                           unsigned long long* __restrict__ slots,
+                                           unsigned long long* __restrict__ slots, uint32_t cap,
                                            DevStatus* __restrict__ status) {
   const uint32_t slot = atomicAdd(&tile_counts[tile], 1u);
-  if (slot < kTileSlots)
-    slots[size_t(tile) * kTileSlots + slot] = key;
-  else if (slot == kTileSlots)
+  if (slot < cap)
+    slots[size_t(tile) * cap + slot] = key;
+  else if (slot == cap)
     status->spill = 1u;
 }
 
@@ -235,6 +236,7 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict_
                                                         uint32_t* __restrict__ big_list,
                                                         uint32_t* __restrict__ big_count,
                                                         unsigned long long* __restrict__ slots,
+                                                        uint32_t slot_cap,
                                                         DevStatus* __restrict__ status) {
   __shared__ uint32_t s_list[kBinWaves][kBinRecPerWave];
   __shared__ uint32_t s_excl[kBinWaves][65];
@@ -271,7 +273,7 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict_
       const int tx = bx.x + k % bx.z, ty = bx.y + k / bx.z;
       const float2 r1 = s_r1[w][j];
       if (record_hits_tile(s_r0[w][j], make_float4(r1.x, r1.y, 0.f, 0.f), V, tx, ty)) {
-        store_slot(global_tile(V, tx, ty), s_key[w][j], tile_counts, slots, status);
+        store_slot(global_tile(V, tx, ty), s_key[w][j], tile_counts, slots, slot_cap, status);
         atomicOr(&s_mask[w][j], 1u << k);
       }
     }
@@ -303,7 +305,8 @@ __device__ __forceinline__ void bin_big_records(uint32_t block, uint32_t n_block
                                                 uint32_t* __restrict__ tile_counts,
                                                 uint32_t* __restrict__ tile_cursor,
                                                 DevStatus* __restrict__ status,
-                                                unsigned long long* __restrict__ comp) {
+                                                unsigned long long* __restrict__ comp,
+                                                uint32_t slot_cap) {
   const uint32_t nb = *big_count;
   for (uint32_t bi = block; bi < nb; bi += n_blocks) {
     const uint32_t rec = big_list[bi];
@@ -317,7 +320,7 @@ __device__ __forceinline__ void bin_big_records(uint32_t block, uint32_t n_block
         if (EMIT)
           comp[atomicAdd(&tile_cursor[global_tile(V, tx, ty)], 1u)] = key;
         else
-          store_slot(global_tile(V, tx, ty), key, tile_counts, comp, status);
+          store_slot(global_tile(V, tx, ty), key, tile_counts, comp, slot_cap, status);
       }
     }
   }
@@ -330,9 +333,10 @@ __global__ void __launch_bounds__(256) bin_big_count_kernel(const float* __restr
                                                             const uint32_t* __restrict__ big_count,
                                                             uint32_t* __restrict__ tile_counts,
                                                             DevStatus* __restrict__ status,
-                                                            unsigned long long* __restrict__ slots) {
+                                                            unsigned long long* __restrict__ slots,
+                                                            uint32_t slot_cap) {
   bin_big_records<false>(blockIdx.x, gridDim.x, records, views, n_views, big_list, big_count,
-                         tile_counts, nullptr, status, slots);
+                         tile_counts, nullptr, status, slots, slot_cap);
 }
 
 // Spill pass: appends (depth bits << 32 | record) of every pair to its
@@ -355,7 +359,7 @@ __global__ void __launch_bounds__(256) bin_emit_kernel(const float* __restrict__
   if (status->overflow || !status->spill) return;
   if (blockIdx.x >= n_small_blocks) {
     bin_big_records<true>(blockIdx.x - n_small_blocks, gridDim.x - n_small_blocks, records, views,
-                          n_views, big_list, big_count, nullptr, tile_cursor, status, comp);
+                          n_views, big_list, big_count, nullptr, tile_cursor, status, comp, 0u);
     return;
   }
   __shared__ uint32_t s_list[kBinWaves][kBinRecPerWave];
@@ -520,13 +524,13 @@ constexpr unsigned kBigBlocks = 1024;
 hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
                             uint32_t n_records, uint32_t* tile_counts, uint32_t* hit_mask,
                             uint32_t* big_list, uint32_t* big_count, unsigned long long* slots,
-                            DevStatus* status, hipStream_t st) {
+                            uint32_t slot_cap, DevStatus* status, hipStream_t st) {
   if (n_records == 0) return hipSuccess;
   hipLaunchKernelGGL(bin_count_kernel, dim3(bin_blocks(n_records)), dim3(256), 0, st, records,
                      views, n_views, n_records, tile_counts, hit_mask, big_list, big_count, slots,
-                     status);
+                     slot_cap, status);
   hipLaunchKernelGGL(bin_big_count_kernel, dim3(kBigBlocks), dim3(256), 0, st, records, views,
-                     n_views, big_list, big_count, tile_counts, status, slots);
+                     n_views, big_list, big_count, tile_counts, status, slots, slot_cap);
   return hipGetLastError();
 }
 

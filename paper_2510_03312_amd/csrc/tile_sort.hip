@@ -2,7 +2,7 @@
 //
 // Binning counts the pairs of every tile (one atomic per pair) and stores
 // the 64-bit key (depth bits << 32 | record) of each in the tile's block of
-// kTileSlots slots, in no particular order; an exclusive scan of the counts
+// tuning.tile_slots slots, in no particular order; an exclusive scan of the counts
 // gives every tile a contiguous segment of the output.  If some tile has
 // more pairs than slots (the spill flag), a second binning pass appends
 // every key to its tile's segment of `comp` through a per-tile cursor
@@ -14,8 +14,7 @@
 // tile_sort_small_kernel: one wavefront per tile (grid-stride over tiles);
 //   writes every tile's range and sorts the tiles of at most kSmallSort
 //   pairs by rank (each key's position is the number of smaller keys in the
-//   tile, LDS broadcast reads); larger tiles (spilled frames only) go to a
-//   list for
+//   tile, LDS broadcast reads); larger tiles go to a list for
 // tile_sort_kernel: one workgroup per listed tile.
 //   n <= kLdsSortMax  bitonic sort in LDS, padded to a power of two;
 //   larger            LSD radix sort of the segment in global memory by the
@@ -34,7 +33,8 @@ constexpr int kTileSortThreads = 256;
 constexpr int kLdsSortMax = 4096;   // keys held in LDS (32 KiB)
 constexpr uint32_t kSmallSort = 256;
 static_assert(kSmallSort == 256, "the rank sort counts for up to four 64-key slots");
-static_assert(kTileSlots == kSmallSort, "a tile sorted by a workgroup implies a spilled frame");
+static_assert(kMaxTileSlots <= uint32_t(kLdsSortMax),
+              "a slot block always fits the LDS sort: the radix sort runs after a spill only");
 
 __device__ __forceinline__ void write_sorted(unsigned long long key, uint32_t tile, size_t pos,
                                              unsigned long long* __restrict__ keys_out,
@@ -138,10 +138,11 @@ __device__ __forceinline__ void count_smaller(const unsigned long long* s_keys, 
 
 __global__ void __launch_bounds__(64) tile_sort_small_kernel(
     const unsigned long long* __restrict__ comp, const unsigned long long* __restrict__ slots,
-    const uint32_t* __restrict__ tile_counts, const uint32_t* __restrict__ tile_cursor,
-    const DevStatus* __restrict__ status, unsigned long long* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, uint32_t* __restrict__ ranges, uint32_t n_tiles,
-    uint32_t* __restrict__ big_tiles, uint32_t* __restrict__ n_big_tiles) {
+    uint32_t slot_cap, const uint32_t* __restrict__ tile_counts,
+    const uint32_t* __restrict__ tile_cursor, const DevStatus* __restrict__ status,
+    unsigned long long* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+    uint32_t* __restrict__ ranges, uint32_t n_tiles, uint32_t* __restrict__ big_tiles,
+    uint32_t* __restrict__ n_big_tiles) {
   __shared__ unsigned long long s_keys[kSmallSort];
   constexpr int Q = int(kSmallSort / 64);
   const uint32_t lane = threadIdx.x;
@@ -152,7 +153,7 @@ __global__ void __launch_bounds__(64) tile_sort_small_kernel(
     // the cursor is the segment start, or its end once the spill pass ran
     const uint32_t start = n ? (spill ? tile_cursor[t] - n : tile_cursor[t]) : 0u;
     const uint32_t end = start + n;   // an empty tile's range is (0, 0)
-    const unsigned long long* src = spill ? comp + start : slots + size_t(t) * kTileSlots;
+    const unsigned long long* src = spill ? comp + start : slots + size_t(t) * slot_cap;
     if (lane == 0) {
       ranges[2 * size_t(t)] = start;
       ranges[2 * size_t(t) + 1] = end;
@@ -189,24 +190,30 @@ __global__ void __launch_bounds__(64) tile_sort_small_kernel(
 }
 
 __global__ void __launch_bounds__(kTileSortThreads) tile_sort_kernel(
-    unsigned long long* __restrict__ comp, const uint32_t* __restrict__ tile_counts,
-    const uint32_t* __restrict__ tile_end, const uint32_t* __restrict__ big_tiles,
-    const uint32_t* __restrict__ n_big_tiles, unsigned long long* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, int digit_bits, int rec_bits) {
+    unsigned long long* __restrict__ comp, const unsigned long long* __restrict__ slots,
+    uint32_t slot_cap, const uint32_t* __restrict__ tile_counts,
+    const uint32_t* __restrict__ tile_cursor, const DevStatus* __restrict__ status,
+    const uint32_t* __restrict__ big_tiles, const uint32_t* __restrict__ n_big_tiles,
+    unsigned long long* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int digit_bits,
+    int rec_bits) {
   __shared__ unsigned long long s_keys[kLdsSortMax];
   __shared__ uint32_t s_hist[4][256];
   __shared__ uint32_t s_lds4[4];
   __shared__ uint32_t s_flag;
   const uint32_t n_big = *n_big_tiles;
+  const bool spill = status->spill != 0u;
   for (uint32_t bt = blockIdx.x; bt < n_big; bt += gridDim.x) {
     const uint32_t t = big_tiles[bt];
     const uint32_t n = tile_counts[t];
-    const uint32_t start = tile_end[t] - n;
+    // the cursor is the segment start, or its end once the spill pass ran;
+    // without a spill the keys are in the tile's slot block (n <= slot_cap)
+    const uint32_t start = spill ? tile_cursor[t] - n : tile_cursor[t];
+    const unsigned long long* src = spill ? comp + start : slots + size_t(t) * slot_cap;
     if (n <= uint32_t(kLdsSortMax)) {
       uint32_t P = 512;
       while (P < n) P <<= 1;
       for (uint32_t i = threadIdx.x; i < P; i += kTileSortThreads)
-        s_keys[i] = i < n ? comp[start + i] : ~0ull;
+        s_keys[i] = i < n ? src[i] : ~0ull;
       __syncthreads();
       for (uint32_t k = 2; k <= P; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
@@ -241,7 +248,8 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_sort_kernel(
 
 // big_tiles: n_tiles words; n_big_tiles must be zero.
 hipError_t launch_tile_sort(unsigned long long* comp, const unsigned long long* slots,
-                            const uint32_t* tile_counts, const uint32_t* tile_cursor,
+                            uint32_t slot_cap, const uint32_t* tile_counts,
+                            const uint32_t* tile_cursor,
                             const DevStatus* status, unsigned long long* keys_out,
                             uint32_t* vals_out, uint32_t* ranges, uint32_t n_tiles,
                             int digit_bits, int rec_bits, uint32_t* big_tiles,
@@ -249,12 +257,12 @@ hipError_t launch_tile_sort(unsigned long long* comp, const unsigned long long* 
   if (n_tiles == 0) return hipSuccess;
   const uint32_t grid = n_tiles < 65536u ? n_tiles : 65536u;
   hipLaunchKernelGGL(tile_sort_small_kernel, dim3(grid), dim3(64), 0, st, comp, slots,
-                     tile_counts, tile_cursor, status, keys_out, vals_out, ranges, n_tiles,
-                     big_tiles, n_big_tiles);
+                     slot_cap, tile_counts, tile_cursor, status, keys_out, vals_out, ranges,
+                     n_tiles, big_tiles, n_big_tiles);
   const uint32_t big_grid = n_tiles < 256u ? n_tiles : 256u;
   hipLaunchKernelGGL(tile_sort_kernel, dim3(big_grid), dim3(kTileSortThreads), 0, st, comp,
-                     tile_counts, tile_cursor, big_tiles, n_big_tiles, keys_out, vals_out,
-                     digit_bits, rec_bits);
+                     slots, slot_cap, tile_counts, tile_cursor, status, big_tiles, n_big_tiles,
+                     keys_out, vals_out, digit_bits, rec_bits);
   return hipGetLastError();
 }
 

@@ -146,15 +146,17 @@ struct DevStatus {
   uint32_t n_visible;
   uint32_t sort_stalled;     // reserved (no bounded wait in the current kernels), 0
   uint32_t work_counter[3];  // persistent raster queues (fwd, bwd, spare)
-  uint32_t spill;            // 1 if some tile met more than kTileSlots records
+  uint32_t spill;            // 1 if some tile met more records than its slot block holds
   uint32_t _pad[6];
 };
 
 static_assert(offsetof(DevStatus, spill) == offsetof(ubs_status_block, spill), "spill offset");
-// Pairs of a tile the counting pass stores directly in the tile's fixed slot
-// block; a frame where some tile has more falls back to a second, emitting
-// pass over the records.
-constexpr uint32_t kTileSlots = 256;
+// Pairs of a tile the counting pass stores directly in the tile's slot block
+// (tuning.tile_slots, default kDefaultTileSlots, at most kMaxTileSlots); a
+// frame where some tile has more falls back to a second, emitting pass over
+// the records.
+constexpr uint32_t kDefaultTileSlots = 256;
+constexpr uint32_t kMaxTileSlots = 4096;
 
 static_assert(sizeof(DevStatus) == sizeof(ubs_status_block), "status block size");
 
@@ -167,7 +169,7 @@ struct Layout {
   uint64_t off_hit_mask;             // per record: hits among its candidate tiles
   uint64_t off_big_list;             // records binned by a workgroup each
   uint64_t off_comp;                 // emitted (depth bits << 32 | record) per tile segment
-  uint64_t off_slots;                // [n_tiles][kTileSlots] keys stored by the counting pass
+  uint64_t off_slots;                // [n_tiles][tile_slots] keys stored by the counting pass
   uint64_t off_keys0, off_values0;   // sorted keys and values
   uint64_t off_tfinal_ws;            // final transmittance kept for the adjoint
   uint64_t off_live, off_live_list, off_live_count;  // per-primitive live flags, compacted list, counts
@@ -178,6 +180,7 @@ struct Layout {
   int64_t n_scan_blocks;
   int32_t rec_bits, digit_bits;
   int32_t tile_w, tile_h;
+  uint32_t tile_slots;
 };
 
 // Scan geometry.

@@ -19,6 +19,10 @@ from ._lib import UbsFrame, UbsLayout, UbsScene, UbsTuning, UbsView
 REC_FIELDS = ("mx", "my", "a", "b", "c", "rho", "o", "beta", "r", "g", "bl", "depth")
 
 
+DEFAULT_TILE_SLOTS = 256   # slot block of a tile when tuning.tile_slots is 0
+MAX_TILE_SLOTS = 4096
+
+
 @dataclasses.dataclass
 class Tuning:
     tile_w: int = 16
@@ -27,10 +31,11 @@ class Tuning:
     digit_bits: int = 8
     pair_capacity: int = 0          # 0: sized from the frame
     flags: int = 0
+    tile_slots: int = 0             # 0: 256, grown by Renderer.forward after a spill
 
     def to_c(self, capacity: int) -> UbsTuning:
         return UbsTuning(self.tile_w, self.tile_h, self.batch_depth, self.digit_bits,
-                         int(capacity), int(self.flags), 0)
+                         int(capacity), int(self.flags), int(self.tile_slots))
 
 
 @dataclasses.dataclass
@@ -88,6 +93,9 @@ class FrameDesc:
     def set_capacity(self, cap: int) -> None:
         self.c.tuning.pair_capacity = int(cap)
 
+    def set_tile_slots(self, slots: int) -> None:
+        self.c.tuning.tile_slots = int(slots)
+
 
 def _stream() -> int:
     return torch.cuda.current_stream().cuda_stream
@@ -107,6 +115,7 @@ class Renderer:
         self.layout: Optional[UbsLayout] = None
         self.frame: Optional[FrameDesc] = None
         self.capacity = int(self.tuning.pair_capacity)
+        self.tile_slots = int(self.tuning.tile_slots)
         self.generation = 0
 
     # ---------------------------------------------------------------- layout
@@ -186,21 +195,33 @@ class Renderer:
         """preprocess -> bin_sort -> render_fwd.  Returns (image, t_final), each
         concatenated over views ([sum HW, 3] and [sum HW]).  With ``check``, reads
         the status once (one stream synchronisation) and reruns with a larger
-        pair capacity if the frame overflowed."""
+        pair capacity if the frame overflowed; if a tile outgrew its slot block
+        (a correct but slower frame) and the tuning leaves tile_slots to the
+        renderer, the blocks are enlarged to fit the longest tile (up to 4096)
+        and the frame is run again."""
         frame = self.make_frame(scenes, views)
         n_pix = sum(int(v.width) * int(v.height) for v in views)
         image = torch.empty((n_pix, 3), dtype=torch.float32, device=self.device)
         t_final = torch.empty((n_pix,), dtype=torch.float32, device=self.device)
-        for _ in range(3):
+        for _ in range(4):
             frame.set_capacity(self.capacity)
+            frame.set_tile_slots(self.tile_slots)
             self.preprocess(frame)
             self.bin_sort(frame)
             if not check:
                 break
             st = self.status()
-            if not st["overflow"]:
-                break
-            self.capacity = int(st["pairs_needed"] * 1.25) + 1024
+            if st["overflow"]:
+                self.capacity = int(st["pairs_needed"] * 1.25) + 1024
+                continue
+            if st["spill"] and self.tuning.tile_slots == 0:
+                rg = self.ranges()
+                longest = int((rg[:, 1] - rg[:, 0]).max().item())
+                want = min(MAX_TILE_SLOTS, -(-int(longest * 1.25) // 64) * 64)
+                if want > max(self.tile_slots, DEFAULT_TILE_SLOTS):
+                    self.tile_slots = want
+                    continue
+            break
         self.render_fwd(frame, image, t_final)
         return image, t_final
 

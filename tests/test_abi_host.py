@@ -53,7 +53,8 @@ def test_ctypes_structs_match_the_header(tmp_path):
     fields = {
         "ubs_scene": ["dim", "rot", "n", "params", "dparams"],
         "ubs_view": ["scene", "width", "height", "R", "t", "fx", "fy", "cx", "cy", "time", "query"],
-        "ubs_tuning": ["tile_w", "tile_h", "batch_depth", "digit_bits", "pair_capacity", "flags"],
+        "ubs_tuning": ["tile_w", "tile_h", "batch_depth", "digit_bits", "pair_capacity", "flags",
+                       "tile_slots"],
         "ubs_frame": ["scenes", "n_scenes", "n_views", "views", "tuning", "stage_events"],
         "ubs_layout": ["bytes", "n_records", "n_tiles", "n_pixels", "pair_capacity", "key_bits",
                        "n_views", "off_status", "off_records", "off_keys", "off_values",
@@ -132,6 +133,9 @@ def test_size_query_without_gpu():
     (lambda f: setattr(f.c.tuning, "digit_bits", 12), _lib.UBS_ERR_UNSUPPORTED),
     (lambda f: setattr(f.c.tuning, "batch_depth", 96), _lib.UBS_ERR_UNSUPPORTED),
     (lambda f: setattr(f.c.tuning, "pair_capacity", -1), _lib.UBS_ERR_ARG),
+    (lambda f: setattr(f.c.tuning, "tile_slots", 128), _lib.UBS_ERR_UNSUPPORTED),
+    (lambda f: setattr(f.c.tuning, "tile_slots", 300), _lib.UBS_ERR_UNSUPPORTED),
+    (lambda f: setattr(f.c.tuning, "tile_slots", 4160), _lib.UBS_ERR_UNSUPPORTED),
     (lambda f: setattr(f._sc[0], "dim", 5), _lib.UBS_ERR_UNSUPPORTED),
     (lambda f: setattr(f._sc[0], "dim", 11), _lib.UBS_ERR_ARG),
     (lambda f: setattr(f._sc[0], "rot", 3), _lib.UBS_ERR_ARG),
@@ -151,6 +155,21 @@ def test_argument_errors_are_reported_before_launch(mutate, code):
     # the other entry points validate the same frame the same way (a bogus,
     # never-dereferenced workspace pointer: validation fails first)
     assert _lib.ubs_bin_sort(f.c, 0x100, 1 << 30, 0, check=False) == code
+
+
+def test_tile_slots_size_the_workspace():
+    """Each tile's slot block takes tuning.tile_slots keys of 8 bytes (0: 256)."""
+    cfg = make_config("cfg0", n=100, width=64, height=64)
+    sizes = {}
+    for slots in (0, 256, 1024, 4096):
+        f = _frame(cfg)
+        f.c.tuning.tile_slots = slots
+        lay = _lib.UbsLayout()
+        assert _lib.ubs_preprocess(f.c, 0, 0, lay, 0) == 0
+        sizes[slots] = lay.bytes
+    assert sizes[0] == sizes[256]
+    assert sizes[1024] - sizes[256] == 16 * 768 * 8
+    assert sizes[4096] - sizes[256] == 16 * 3840 * 8
 
 
 def test_workspace_checks():

@@ -63,9 +63,9 @@ def test_preprocess_records_match_oracle(case):
 
 
 # ------------------------------------------------------------------ bin + sort
-def _inject_and_sort(cfg, recs):
+def _inject_and_sort(cfg, recs, tile_slots=0):
     from paper_2510_03312_amd import Renderer, SceneRef, Tuning
-    r = Renderer(Tuning(pair_capacity=1 << 20))
+    r = Renderer(Tuning(pair_capacity=1 << 20, tile_slots=tile_slots))
     scenes = [SceneRef(to_dev(s.params), s.dim, s.rot) for s in cfg["scenes"]]
     frame = r.make_frame(scenes, cfg["views"])
     r.preprocess(frame)
@@ -113,12 +113,15 @@ def test_bin_sort_bit_exact_multi_view():
     np.testing.assert_array_equal(ranges, rg)
 
 
-@pytest.mark.parametrize("n0,n1", [(256, 255), (256, 257), (257, 1), (0, 256), (1, 0)])
-def test_bin_sort_at_the_tile_slot_capacity(n0, n1):
-    """Two 16x16 tiles holding exactly n0 and n1 pairs: up to 256 pairs a
-    tile the keys come from the counting pass's slot blocks, one more sends
-    the whole frame through the emitting pass."""
-    log(f"[bin_sort] slot capacity {n0}/{n1}")
+@pytest.mark.parametrize("n0,n1,slots", [(256, 255, 0), (256, 257, 0), (257, 1, 0), (0, 256, 0),
+                                         (1, 0, 0), (512, 511, 512), (512, 513, 512),
+                                         (300, 100, 1024)])
+def test_bin_sort_at_the_tile_slot_capacity(n0, n1, slots):
+    """Two 16x16 tiles holding exactly n0 and n1 pairs: up to the slot
+    capacity (256 by default) a tile's keys come from the counting pass's
+    slot blocks, one more sends the whole frame through the emitting pass;
+    tiles of more than 256 pairs are sorted by a workgroup from either."""
+    log(f"[bin_sort] slot capacity {n0}/{n1} slots={slots}")
     n = n0 + n1
     cfg = make_config("cfg0", n=n, width=32, height=16)
     recs = make_splat_records(n, 32, 16, seed=21, cull_frac=0.0, max_extent=1.0)
@@ -131,27 +134,28 @@ def test_bin_sort_at_the_tile_slot_capacity(n0, n1):
         recs[:20, 11] = recs[20:40, 11]      # exact depth ties
     sk, sv, rg = bin_reference(recs, [_V(cfg["views"][0], recs.shape[0])])
     assert list((rg[:, 1] - rg[:, 0]).astype(int)) == [n0, n1]
-    r, frame, K, keys, vals, ranges = _inject_and_sort(cfg, recs)
-    assert r.status()["spill"] == int(max(n0, n1) > 256)
+    r, frame, K, keys, vals, ranges = _inject_and_sort(cfg, recs, tile_slots=slots)
+    assert r.status()["spill"] == int(max(n0, n1) > (slots or 256))
     assert K == sk.size
     np.testing.assert_array_equal(keys, sk)
     np.testing.assert_array_equal(vals, sv)
     np.testing.assert_array_equal(ranges, rg)
 
 
+@pytest.mark.parametrize("slots", [0, 4096])
 @pytest.mark.parametrize("digit_bits", [4, 5, 7, 8])
 @pytest.mark.parametrize("n,W,H,ext", [(2000, 300, 200, 30.0),    # short segments: rank sort
                                        (3000, 64, 48, 40.0),      # 395-519 per tile: bitonic
                                        (9000, 24, 20, 40.0)])     # 5459 in one tile: radix
-def test_sort_paths_and_digit_widths_agree(digit_bits, n, W, H, ext):
+def test_sort_paths_and_digit_widths_agree(digit_bits, n, W, H, ext, slots):
     from paper_2510_03312_amd import Tuning
-    log(f"[bin_sort] digit_bits={digit_bits} n={n} {W}x{H}")
+    log(f"[bin_sort] digit_bits={digit_bits} n={n} {W}x{H} slots={slots}")
     cfg = make_config("cfg0", n=n, width=W, height=H)
     recs = make_splat_records(n, W, H, seed=5, max_extent=ext)
     recs[:50, 11] = recs[50:100, 11]          # exact depth ties
     sk, sv, rg = bin_reference(recs, [_V(cfg["views"][0], n)])
     from paper_2510_03312_amd import Renderer, SceneRef
-    r = Renderer(Tuning(pair_capacity=1 << 18, digit_bits=digit_bits))
+    r = Renderer(Tuning(pair_capacity=1 << 18, digit_bits=digit_bits, tile_slots=slots))
     frame = r.make_frame([SceneRef(to_dev(cfg["scenes"][0].params), 3, 0)], cfg["views"])
     r.preprocess(frame)
     r.records().copy_(to_dev(recs))
@@ -160,6 +164,7 @@ def test_sort_paths_and_digit_widths_agree(digit_bits, n, W, H, ext):
     assert K == sk.size
     per_tile = (rg[:, 1] - rg[:, 0]).astype(np.int64)
     log(f"  pairs {K}, longest segment {per_tile.max()}")
+    assert r.status()["spill"] == int(per_tile.max() > (slots or 256))
     keys, vals = r.sorted_pairs(K)
     np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint64), sk)
     np.testing.assert_array_equal(vals.cpu().numpy().view(np.uint32), sv)
@@ -409,6 +414,28 @@ def test_determinism():
     v = grad_violations(a["dparams"][0], b["dparams"][0].astype(np.float64), rtol=1e-4, floor=1e-3)
     assert v.sum() == 0
     assert a["status"]["sort_stalled"] == 0 and b["status"]["sort_stalled"] == 0
+
+
+def test_forward_grows_tile_slots_after_a_spill():
+    """A frame with tiles of up to 1816 pairs: with 256 slots it takes the
+    emitting pass; the renderer left to size the slots enlarges them, reruns
+    without a spill, and draws the same image bit for bit."""
+    from paper_2510_03312_amd import Renderer, SceneRef, Tuning
+    log("[bin_sort] slot growth")
+    cfg = make_config("cfg0", n=6000, width=64, height=48)
+    sc = cfg["scenes"][0]
+    scenes = [SceneRef(to_dev(sc.params), sc.dim, sc.rot)]
+    fixed = Renderer(Tuning(tile_slots=256))
+    img_fixed, tf_fixed = fixed.forward(scenes, cfg["views"])
+    assert fixed.status()["spill"] == 1 and fixed.tile_slots == 256
+    auto = Renderer()
+    img_auto, tf_auto = auto.forward(scenes, cfg["views"])
+    rg = auto.ranges().cpu().numpy()
+    longest = int((rg[:, 1] - rg[:, 0]).max())
+    assert 256 < longest <= auto.tile_slots <= 4096
+    assert auto.status()["spill"] == 0
+    assert torch.equal(img_fixed, img_auto) and torch.equal(tf_fixed, tf_auto)
+    np.testing.assert_array_equal(fixed.ranges().cpu().numpy(), rg)
 
 
 @pytest.mark.parametrize("case", ["cfg0_3d_quat", "cfg1_6d_ragged", "headline_7d_ragged"])
