@@ -259,7 +259,8 @@ hipError_t launch_tile_sort(unsigned long long* comp, const unsigned long long* 
   hipLaunchKernelGGL(tile_sort_small_kernel, dim3(grid), dim3(64), 0, st, comp, slots,
                      slot_cap, tile_counts, tile_cursor, status, keys_out, vals_out, ranges,
                      n_tiles, big_tiles, n_big_tiles);
-  const uint32_t big_grid = n_tiles < 256u ? n_tiles : 256u;
+  // up to four workgroups per CU (the LDS sort takes 37 KiB of the 160)
+  const uint32_t big_grid = n_tiles < 1024u ? n_tiles : 1024u;
   hipLaunchKernelGGL(tile_sort_kernel, dim3(big_grid), dim3(kTileSortThreads), 0, st, comp,
                      slots, slot_cap, tile_counts, tile_cursor, status, big_tiles, n_big_tiles,
                      keys_out, vals_out, digit_bits, rec_bits);
