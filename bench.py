@@ -106,7 +106,9 @@ def recorded_traffic(workload: str, kernel: str):
 
 
 def stage_bytes(stage: str, c: dict) -> float:
-    """Algorithmic HBM bytes of one launch of a stage."""
+    """Algorithmic HBM bytes of one launch of a stage: the bytes its inputs and
+    outputs must move at least once (records 48 B, pairs 8-12 B, pixels 12-32 B,
+    parameters 4 B per row entry)."""
     P, F, R, Pv, K, A, G = c["P"], c["F"], c["R"], c["Pv"], c["K"], c["A"], c["G"]
     return {
         "preprocess": 4.0 * F * P + 48.0 * R,

@@ -29,12 +29,6 @@ CASES = {
 }
 
 
-def _dump(name, **arrays):
-    import os
-    os.makedirs("gpurun_out", exist_ok=True)
-    np.savez_compressed(os.path.join("gpurun_out", name + ".npz"), **arrays)
-
-
 def _cfg(name):
     base, kw = CASES[name]
     return make_config(base, **kw)
@@ -235,8 +229,6 @@ def test_gradients_match_oracle(case):
     o = oracle_view(cfg, 0, d_image=dimg)
     g = gpu_render(cfg, want_grad=True, d_images=[dimg])
     sc = cfg["scenes"][0]
-    _dump(f"grad_{case}", dparams=g["dparams"][0], grad2d=g["grad2d"], records=g["records"],
-          ref=o["dparams"], d_rec=o["d_rec"], noise=o["dparams_noise"], dimg=dimg)
     total_bad = 0
     for name, s in _block_slices(sc.dim, sc.rot).items():
         gg, go = g["dparams"][0][s], o["dparams"][s]
