@@ -99,8 +99,7 @@ __device__ __forceinline__ bool record_hits_tile(const float4 r0, const float4 r
 
 // Records whose conservative tile box holds at most kSmallBox candidate tiles
 // go through their wavefront's flat candidate list, their hits kept as one
-// bit per candidate; larger ones are binned by bin_big_kernel, a workgroup
-// per record.
+// bit per candidate; larger ones are binned by their whole workgroup.
 constexpr int kSmallBox = 32;
 static_assert(kSmallBox <= 32, "hit masks are 32 bits");
 
@@ -206,14 +205,6 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
   return v;
 }
 
-// One atomic increment of tile_counts per (tile, record) pair.  Records with
-// at most kSmallBox candidate tiles are binned 64 at a time by the whole
-// wavefront: their candidates form one flat list (record order, row-major
-// candidates) that the lanes take in turns, so a wavefront runs as many
-// rounds of tile tests as it has candidates / 64 rather than as its largest
-// record has candidates.  The hits of each record (bit k: candidate k) are
-// kept as a mask for the emission.  Larger records are appended to
-// big_list and binned by bin_big_kernel, a workgroup per record.
 // Counts one pair of `tile` and stores its key in the tile's block of `cap`
 // slots while the block has room; the first pair beyond it raises the spill
 // flag.
@@ -228,6 +219,15 @@ __device__ __forceinline__ void store_slot(uint32_t tile, unsigned long long key
     status->spill = 1u;
 }
 
+// One atomic increment of tile_counts per (tile, record) pair, the key
+// stored in the tile's slot block.  Records with at most kSmallBox candidate
+// tiles are binned 64 at a time by the whole wavefront: their candidates form
+// one flat list (record order, row-major candidates) that the lanes take in
+// turns, so a wavefront runs as many rounds of tile tests as it has
+// candidates / 64 rather than as its largest record has candidates.  The
+// hits of each record (bit k: candidate k) are kept as a mask for the spill
+// pass.  Larger records are binned at the end by the whole workgroup, one at
+// a time, and appended to big_list for the spill pass.
 __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict__ records,
                                                         const DevView* __restrict__ views,
                                                         int n_views, uint32_t n_records,
@@ -245,8 +245,12 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict_
   __shared__ float2 s_r1[kBinWaves][64];
   __shared__ int4 s_box[kBinWaves][64];     // tx0, ty0, box width, view
   __shared__ uint32_t s_mask[kBinWaves][64];
+  __shared__ uint32_t s_big[kBinWaves * kBinRecPerWave];   // the workgroup's big records
+  __shared__ uint32_t s_nbig;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  if (threadIdx.x == 0) s_nbig = 0u;
+  __syncthreads();
   uint32_t* list = s_list[w];
   const uint32_t cnt = gather_live(records, n_records, list);
   for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
@@ -282,31 +286,51 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict_
     const bool big = b.n_cand > kSmallBox;
     const unsigned long long bm = __ballot(big);
     if (bm) {
-      uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(big_count, uint32_t(__popcll(bm)));
+      // listed for the workgroup below, and globally for the spill pass
+      uint32_t base = 0, lbase = 0;
+      if (lane == 0) {
+        base = atomicAdd(big_count, uint32_t(__popcll(bm)));
+        lbase = atomicAdd(&s_nbig, uint32_t(__popcll(bm)));
+      }
       base = uint32_t(__shfl(int(base), 0, 64));
-      if (big) big_list[base + uint32_t(__popcll(bm & lt_mask))] = rec;
+      lbase = uint32_t(__shfl(int(lbase), 0, 64));
+      const uint32_t below = uint32_t(__popcll(bm & lt_mask));
+      if (big) {
+        big_list[base + below] = rec;
+        s_big[lbase + below] = rec;
+      }
     }
     __builtin_amdgcn_wave_barrier();
   }
+  // the records with more than kSmallBox candidates: the whole workgroup
+  // tests the candidates of one at a time
+  __syncthreads();
+  const uint32_t nb = s_nbig;
+  for (uint32_t bi = 0; bi < nb; ++bi) {
+    const uint32_t rec = s_big[bi];
+    const BinRec o = load_bin_rec(records, views, n_views, rec, true);
+    const DevView& V = views[o.view];
+    const int bw = o.box.tx1 - o.box.tx0 + 1;
+    const unsigned long long key = ((unsigned long long)__float_as_uint(o.depth) << 32) | rec;
+    for (int k = int(threadIdx.x); k < o.n_cand; k += 256) {
+      const int tx = o.box.tx0 + k % bw, ty = o.box.ty0 + k / bw;
+      if (record_hits_tile(o.r0, o.r1, V, tx, ty))
+        store_slot(global_tile(V, tx, ty), key, tile_counts, slots, slot_cap, status);
+    }
+  }
 }
 
-// Records with more than kSmallBox candidate tiles: a workgroup per record
-// (grid-stride over big_list), its threads testing consecutive candidates.
-// EMIT = false counts the hits into tile_counts and stores them in the slot
-// blocks, EMIT = true appends them to the tile segments (spill fallback).
-// Workgroup `block` of `n_blocks` takes records block, block + n_blocks, ...
-template <bool EMIT>
-__device__ __forceinline__ void bin_big_records(uint32_t block, uint32_t n_blocks,
-                                                const float* __restrict__ records,
-                                                const DevView* __restrict__ views, int n_views,
-                                                const uint32_t* __restrict__ big_list,
-                                                const uint32_t* __restrict__ big_count,
-                                                uint32_t* __restrict__ tile_counts,
-                                                uint32_t* __restrict__ tile_cursor,
-                                                DevStatus* __restrict__ status,
-                                                unsigned long long* __restrict__ comp,
-                                                uint32_t slot_cap) {
+// Spill pass, records with more than kSmallBox candidate tiles: a workgroup
+// per record (grid-stride over big_list; workgroup `block` of `n_blocks`
+// takes records block, block + n_blocks, ...), its threads testing
+// consecutive candidates and appending the hits to the tile segments.
+__device__ __forceinline__ void emit_big_records(uint32_t block, uint32_t n_blocks,
+                                                 const float* __restrict__ records,
+                                                 const DevView* __restrict__ views, int n_views,
+                                                 const uint32_t* __restrict__ big_list,
+                                                 const uint32_t* __restrict__ big_count,
+                                                 uint32_t* __restrict__ tile_cursor,
+                                                 unsigned long long* __restrict__ comp) {
   const uint32_t nb = *big_count;
   for (uint32_t bi = block; bi < nb; bi += n_blocks) {
     const uint32_t rec = big_list[bi];
@@ -316,27 +340,10 @@ __device__ __forceinline__ void bin_big_records(uint32_t block, uint32_t n_block
     const unsigned long long key = ((unsigned long long)__float_as_uint(o.depth) << 32) | rec;
     for (int k = int(threadIdx.x); k < o.n_cand; k += 256) {
       const int tx = o.box.tx0 + k % bw, ty = o.box.ty0 + k / bw;
-      if (record_hits_tile(o.r0, o.r1, V, tx, ty)) {
-        if (EMIT)
-          comp[atomicAdd(&tile_cursor[global_tile(V, tx, ty)], 1u)] = key;
-        else
-          store_slot(global_tile(V, tx, ty), key, tile_counts, comp, slot_cap, status);
-      }
+      if (record_hits_tile(o.r0, o.r1, V, tx, ty))
+        comp[atomicAdd(&tile_cursor[global_tile(V, tx, ty)], 1u)] = key;
     }
   }
-}
-
-__global__ void __launch_bounds__(256) bin_big_count_kernel(const float* __restrict__ records,
-                                                            const DevView* __restrict__ views,
-                                                            int n_views,
-                                                            const uint32_t* __restrict__ big_list,
-                                                            const uint32_t* __restrict__ big_count,
-                                                            uint32_t* __restrict__ tile_counts,
-                                                            DevStatus* __restrict__ status,
-                                                            unsigned long long* __restrict__ slots,
-                                                            uint32_t slot_cap) {
-  bin_big_records<false>(blockIdx.x, gridDim.x, records, views, n_views, big_list, big_count,
-                         tile_counts, nullptr, status, slots, slot_cap);
 }
 
 // Spill pass: appends (depth bits << 32 | record) of every pair to its
@@ -358,8 +365,8 @@ __global__ void __launch_bounds__(256) bin_emit_kernel(const float* __restrict__
                                                        unsigned long long* __restrict__ comp) {
   if (status->overflow || !status->spill) return;
   if (blockIdx.x >= n_small_blocks) {
-    bin_big_records<true>(blockIdx.x - n_small_blocks, gridDim.x - n_small_blocks, records, views,
-                          n_views, big_list, big_count, nullptr, tile_cursor, status, comp, 0u);
+    emit_big_records(blockIdx.x - n_small_blocks, gridDim.x - n_small_blocks, records, views,
+                     n_views, big_list, big_count, tile_cursor, comp);
     return;
   }
   __shared__ uint32_t s_list[kBinWaves][kBinRecPerWave];
@@ -529,8 +536,6 @@ hipError_t launch_bin_count(const float* records, const DevView* views, int n_vi
   hipLaunchKernelGGL(bin_count_kernel, dim3(bin_blocks(n_records)), dim3(256), 0, st, records,
                      views, n_views, n_records, tile_counts, hit_mask, big_list, big_count, slots,
                      slot_cap, status);
-  hipLaunchKernelGGL(bin_big_count_kernel, dim3(kBigBlocks), dim3(256), 0, st, records, views,
-                     n_views, big_list, big_count, tile_counts, status, slots, slot_cap);
   return hipGetLastError();
 }
 
