@@ -107,6 +107,34 @@ def test_bin_sort_bit_exact_multi_view():
     np.testing.assert_array_equal(ranges, rg)
 
 
+@pytest.mark.parametrize("slots", [0, 1024])
+def test_bin_sort_multi_view_with_a_spilling_view(slots):
+    """Six views, one of them crowded (tiles of several hundred pairs): with
+    256 slots the whole frame takes the emitting pass, with 1024 it does not;
+    keys, values and ranges are bit-exact either way."""
+    log(f"[bin_sort] multi-view spill slots={slots}")
+    cfg = make_config("cfg4", scene_sizes=(700, 300, 2500, 100), n_views=6)
+    sizes = [(64, 48), (100, 30), (40, 40), (128, 128), (16, 16), (90, 70)]
+    for v, (w, h) in zip(cfg["views"], sizes):
+        v.width, v.height = w, h
+    ns = [cfg["scenes"][v.scene].n for v in cfg["views"]]
+    recs = []
+    for k, (n, v) in enumerate(zip(ns, cfg["views"])):
+        crowded = v.width == 40
+        recs.append(make_splat_records(n, v.width, v.height, seed=30 + k,
+                                       max_extent=30.0 if crowded else 8.0))
+    recs = np.concatenate(recs)
+    sk, sv, rg = bin_reference(recs, [_V(v, n) for v, n in zip(cfg["views"], ns)])
+    longest = int((rg[:, 1] - rg[:, 0]).max())
+    assert 256 < longest <= 1024, longest
+    r, frame, K, keys, vals, ranges = _inject_and_sort(cfg, recs, tile_slots=slots)
+    assert r.status()["spill"] == int(slots == 0)
+    assert K == sk.size
+    np.testing.assert_array_equal(keys, sk)
+    np.testing.assert_array_equal(vals, sv)
+    np.testing.assert_array_equal(ranges, rg)
+
+
 @pytest.mark.parametrize("n0,n1,slots", [(256, 255, 0), (256, 257, 0), (257, 1, 0), (0, 256, 0),
                                          (1, 0, 0), (512, 511, 512), (512, 513, 512),
                                          (300, 100, 1024)])
