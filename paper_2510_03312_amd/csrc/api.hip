@@ -82,6 +82,30 @@ __global__ void fill_f32_kernel(float* __restrict__ p, size_t n) {
   for (size_t k = i; k < n; k += stride) store_stream(&p[k], 0.0f);
 }
 
+// Same with 16-byte stores: p 16-byte aligned; the n % 4 tail by thread 0.
+__global__ void fill_f32x4_kernel(float* __restrict__ p, size_t n) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  float4* q = reinterpret_cast<float4*>(p);
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (size_t k = i; k < n / 4; k += stride) store_stream(&q[k], z);
+  if (i == 0)
+    for (size_t k = n & ~size_t(3); k < n; ++k) store_stream(&p[k], 0.0f);
+}
+
+// Zeroes n floats at p (one launch; none for n == 0).
+static void launch_fill_zero(float* p, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  const bool vec = (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+  const size_t items = vec ? (n + 3) / 4 : n;
+  size_t blocks = (items + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (vec)
+    hipLaunchKernelGGL(fill_f32x4_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, p, n);
+  else
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, p, n);
+}
+
 // Records a stage event on the call's stream.
 static void stage_mark(const ubs_frame* f, int stage, int end, hipStream_t s) {
   if (f->stage_events) {
@@ -201,9 +225,8 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.rec_bits = n_rec > 1 ? ceil_log2_u64(n_rec) : 1;
   const uint64_t cap = uint64_t(tu.pair_capacity);
   l.n_prims = int64_t(n_prims);
-  // the scans run over the tile counts and over the primitives' live flags
-  const uint64_t scan_n = n_tiles > n_prims ? n_tiles : n_prims;
-  l.n_scan_blocks = int64_t((scan_n + kScanTile - 1) / kScanTile);
+  // the one scan of a frame runs over the tile counts
+  l.n_scan_blocks = int64_t((n_tiles + kScanTile - 1) / kScanTile);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) { const uint64_t o = off; off = align256(off + bytes); return o; };
   l.pub.off_status = take(sizeof(DevStatus));
@@ -428,11 +451,7 @@ ubs_status ubs_render_bwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
   float* grad2d = at<float>(ws, L.pub.off_grad2d);
   const size_t ng = size_t(L.pub.n_records) * kGradFloats;
   stage_mark(frame, UBS_STAGE_GRAD_CLEAR, 0, s);
-  if (ng > 0) {
-    size_t blocks = (ng + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(fill_f32_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, grad2d, ng);
-  }
+  launch_fill_zero(grad2d, ng, s);
   stage_mark(frame, UBS_STAGE_GRAD_CLEAR, 1, s);
   const float l1_scale = L.pub.n_pixels > 0 ? float(1.0 / (3.0 * double(L.pub.n_pixels))) : 0.0f;
   const DevView* views = at<DevView>(ws, L.off_views);
@@ -452,11 +471,7 @@ ubs_status ubs_render_bwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
     bool used = false;
     for (const DevView& v : p.dv) used = used || v.scene == sc;
     if (!used) {  // a scene no view sees has zero gradient
-      const size_t nf = size_t(p.ds[sc].F) * size_t(p.ds[sc].n);
-      size_t blocks = (nf + 255) / 256;
-      if (blocks > 8192) blocks = 8192;
-      hipLaunchKernelGGL(fill_f32_kernel, dim3(unsigned(blocks)), dim3(256), 0, s,
-                         p.ds[sc].dparams, nf);
+      launch_fill_zero(p.ds[sc].dparams, size_t(p.ds[sc].F) * size_t(p.ds[sc].n), s);
       continue;
     }
     // the adjoint runs only for the primitives some view kept (listed by

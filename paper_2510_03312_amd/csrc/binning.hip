@@ -545,6 +545,7 @@ hipError_t launch_bin_count(const float* records, const DevView* views, int n_vi
 constexpr uint32_t kSingleScanMax = 16u * kScanTile;
 constexpr int kSingleThreads = 1024;
 constexpr int kSingleItems = 8;
+static_assert(kSingleItems == 8, "the vector path loads and stores two uint4 per thread");
 constexpr uint32_t kSingleChunk = uint32_t(kSingleThreads * kSingleItems);
 
 __global__ void __launch_bounds__(kSingleThreads) scan_single_kernel(
@@ -555,6 +556,7 @@ __global__ void __launch_bounds__(kSingleThreads) scan_single_kernel(
   __shared__ uint32_t s_wave[W];
   __shared__ unsigned long long s_wave64[W];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u) == 0;
   uint32_t carry = 0;
   unsigned long long total = 0;
   for (uint32_t c0 = 0; c0 < n; c0 += kSingleChunk) {
@@ -562,9 +564,18 @@ __global__ void __launch_bounds__(kSingleThreads) scan_single_kernel(
     uint32_t vals[kSingleItems];
     uint32_t sum = 0;
     unsigned long long sum64 = 0;
+    if (vec && base + kSingleItems <= n) {
+      // two 16-byte loads (in is 16-byte aligned, base a multiple of 8)
+      const uint4 v0 = *reinterpret_cast<const uint4*>(in + base);
+      const uint4 v1 = *reinterpret_cast<const uint4*>(in + base + 4);
+      vals[0] = v0.x; vals[1] = v0.y; vals[2] = v0.z; vals[3] = v0.w;
+      vals[4] = v1.x; vals[5] = v1.y; vals[6] = v1.z; vals[7] = v1.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < kSingleItems; ++k) vals[k] = base + k < n ? in[base + k] : 0u;
+    }
 #pragma unroll
     for (int k = 0; k < kSingleItems; ++k) {
-      vals[k] = base + k < n ? in[base + k] : 0u;
       sum += vals[k];
       sum64 += vals[k];
     }
@@ -592,13 +603,21 @@ __global__ void __launch_bounds__(kSingleThreads) scan_single_kernel(
     }
     __syncthreads();
     uint32_t run = carry + before + x - sum;
+    if (vec && list == nullptr && base + kSingleItems <= n) {
+      uint32_t o[kSingleItems];
 #pragma unroll
-    for (int k = 0; k < kSingleItems; ++k) {
-      if (base + k < n) {
-        out[base + k] = run;
-        if (list != nullptr && vals[k] != 0u) list[run] = base + k;
+      for (int k = 0; k < kSingleItems; ++k) { o[k] = run; run += vals[k]; }
+      *reinterpret_cast<uint4*>(out + base) = make_uint4(o[0], o[1], o[2], o[3]);
+      *reinterpret_cast<uint4*>(out + base + 4) = make_uint4(o[4], o[5], o[6], o[7]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < kSingleItems; ++k) {
+        if (base + k < n) {
+          out[base + k] = run;
+          if (list != nullptr && vals[k] != 0u) list[run] = base + k;
+        }
+        run += vals[k];
       }
-      run += vals[k];
     }
     carry += chunk;
     total += chunk64;
