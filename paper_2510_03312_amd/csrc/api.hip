@@ -254,7 +254,8 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.off_live_count = take(4 * uint64_t(kKeptLists) * uint64_t(f->n_scenes > 0 ? f->n_scenes : 1));
   l.off_grad_compact = take(4 * n_grad_compact);
   // per-workgroup counts of the preprocess launches (one launch per scene)
-  l.n_pre_partials = int64_t(n_prims / 256 + uint64_t(f->n_scenes) + 1);
+  // a multiple of 4, so that both halves of the table are 16-byte aligned
+  l.n_pre_partials = int64_t((n_prims / 256 + uint64_t(f->n_scenes) + 1 + 3) & ~uint64_t(3));
   l.off_pre_partials = take(8 * uint64_t(l.n_pre_partials));
   l.pub.bytes = off;
   l.pub.off_keys = l.off_keys0;

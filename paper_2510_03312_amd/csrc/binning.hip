@@ -690,8 +690,21 @@ __global__ void __launch_bounds__(256) bin_prepare_kernel(uint32_t* __restrict__
   if (blockIdx.x != 0) return;
   __shared__ uint32_t s_sum[2][4];
   uint32_t vis = 0, nf = 0;
-#pragma unroll 8
-  for (uint32_t k = threadIdx.x; k < n_partials; k += 256) {
+  uint32_t k0 = 0;
+  if ((stride & 3u) == 0 && (reinterpret_cast<uintptr_t>(partial) & 15u) == 0) {
+    // 16-byte loads over both halves (stride a multiple of 4)
+    const uint4* pv = reinterpret_cast<const uint4*>(partial);
+    const uint4* pn = reinterpret_cast<const uint4*>(partial + stride);
+    const uint32_t n4 = n_partials / 4;
+#pragma unroll 4
+    for (uint32_t k = threadIdx.x; k < n4; k += 256) {
+      const uint4 a = pv[k], b = pn[k];
+      vis += (a.x + a.y) + (a.z + a.w);
+      nf += (b.x + b.y) + (b.z + b.w);
+    }
+    k0 = n4 * 4;
+  }
+  for (uint32_t k = k0 + threadIdx.x; k < n_partials; k += 256) {
     vis += partial[k];
     nf += partial[stride + k];
   }
