@@ -1,7 +1,8 @@
 // Tile binning: per-tile pair counts, with every (tile, record) key stored
-// in the tile's fixed block of slots in the same pass; for a frame where some
-// tile outgrows its block, a second pass emits every pair into its tile's
-// segment (the segments come from an exclusive scan of the counts).  The
+// in the tile's block of slots (tuning.tile_slots) in the same pass; for a
+// frame where some tile outgrows its block, a second pass emits every pair
+// into its tile's segment (the segments come from an exclusive scan of the
+// counts).  The
 // order inside a tile is fixed afterwards by tile_sort.hip.
 //
 // A record overlaps a tile iff the minimum of its quadratic form
