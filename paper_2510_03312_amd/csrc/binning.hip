@@ -2,8 +2,7 @@
 // in the tile's block of slots (tuning.tile_slots) in the same pass; for a
 // frame where some tile outgrows its block, a second pass emits every pair
 // into its tile's segment (the segments come from an exclusive scan of the
-// counts).  The
-// order inside a tile is fixed afterwards by tile_sort.hip.
+// counts).  The order inside a tile is fixed afterwards by tile_sort.hip.
 //
 // A record overlaps a tile iff the minimum of its quadratic form
 // r(p) = a dx^2 + 2 b dx dy + c dy^2 over the rectangle spanned by the
