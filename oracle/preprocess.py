@@ -277,6 +277,14 @@ def project(mu_c: torch.Tensor, S_c: torch.Tensor, view):
     return mean2d, Sp, z
 
 
+def conic(Sp: torch.Tensor, det: torch.Tensor):
+    """The conic A = Sigma'^-1 of a 2x2 covariance, as (a, b, c) with
+    r = a dx^2 + 2 b dx dy + c dy^2 the squared Mahalanobis distance
+    (Section 3, equation r).  ``det`` is det Sigma' (any nonzero value for a
+    culled splat)."""
+    return Sp[:, 1, 1] / det, -Sp[:, 0, 1] / det, Sp[:, 0, 0] / det
+
+
 # --------------------------------------------------------------------------
 # full per-primitive step: parameters -> screen-space records
 # --------------------------------------------------------------------------
@@ -315,10 +323,7 @@ def preprocess(params: torch.Tensor, dim: int, rot: int, view,
     det = Sp[:, 0, 0] * Sp[:, 1, 1] - Sp[:, 0, 1] * Sp[:, 1, 0]
     valid = (depth > NEAR_PLANE) & (det > 0) & (Sp[:, 0, 0] > 0) & (Sp[:, 1, 1] > 0) \
         & (o_q >= ALPHA_MIN)
-    dets = torch.where(valid, det, torch.ones_like(det))
-    a = Sp[:, 1, 1] / dets
-    b = -Sp[:, 0, 1] / dets
-    c = Sp[:, 0, 0] / dets
+    a, b, c = conic(Sp, torch.where(valid, det, torch.ones_like(det)))
     beta_x = beta_of_b(f["b_x"][0])
     o_qs = torch.where(valid, o_q, torch.ones_like(o_q))
     rho = 1.0 - (255.0 * o_qs) ** (-1.0 / beta_x)

@@ -33,21 +33,26 @@ def lib():
         path = _build.LIB
         if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
             _build.build()
-        L = ctypes.CDLL(path)
-        L.oracle_render_fwd.argtypes = [ctypes.c_int, _D, _U8, ctypes.c_int, ctypes.c_int,
-                                        ctypes.c_int, ctypes.c_int, _D, _D, _D, _I, _U]
-        L.oracle_render_pixels.argtypes = [ctypes.c_int, _D, _U8, ctypes.c_int, ctypes.c_int,
-                                           ctypes.c_int, _I, _I, _D, _D, _D, _I, _U]
-        L.oracle_render_bwd.argtypes = [ctypes.c_int, _D, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                        ctypes.c_int, _D, _D, _D, _D]
-        L.oracle_bin.restype = ctypes.c_int64
-        L.oracle_bin.argtypes = [ctypes.c_int, _F, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                 ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
-                                 _U64, _U32]
-        L.oracle_tile_hit.argtypes = [ctypes.c_double] * 10
-        L.oracle_tile_hit.restype = ctypes.c_int
-        _lib = L
+        _lib = load(path)
     return _lib
+
+
+def load(path: str):
+    """Open a build of ``raster.c`` at ``path`` and declare its signatures."""
+    L = ctypes.CDLL(path)
+    L.oracle_render_fwd.argtypes = [ctypes.c_int, _D, _U8, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, _D, _D, _D, _I, _U]
+    L.oracle_render_pixels.argtypes = [ctypes.c_int, _D, _U8, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, _I, _I, _D, _D, _D, _I, _U]
+    L.oracle_render_bwd.argtypes = [ctypes.c_int, _D, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, _D, _D, _D, _D]
+    L.oracle_bin.restype = ctypes.c_int64
+    L.oracle_bin.argtypes = [ctypes.c_int, _F, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
+                             _U64, _U32]
+    L.oracle_tile_hit.argtypes = [ctypes.c_double] * 10
+    L.oracle_tile_hit.restype = ctypes.c_int
+    return L
 
 
 def _p(a, t):

@@ -535,6 +535,43 @@ def test_early_termination_golden():
     assert tf[3, 4] == pytest.approx(g["t_final"], abs=1e-18)
 
 
+def test_stop_ends_the_pixel():
+    """The pixel stops at the first record that would take T below 1e-4, and
+    records behind it are not composited even when they alone would keep T
+    above 1e-4: alphas 0.9, 0.9, 0.9 leave T = 1e-3; the next (0.95) would
+    leave 5e-5, so the pixel ends with colour 1 - 1e-3 although a record of
+    alpha 0.5 follows."""
+    alphas = [0.9, 0.9, 0.9, 0.95, 0.5]
+    rec = np.zeros((len(alphas), 12))
+    rec[:, :5] = [4.5, 3.5, 0.2, 0.0, 0.2]
+    rec[:, 5] = 0.9
+    rec[:, 6] = alphas
+    rec[:, 7] = 4.0
+    rec[:, 8:11] = 1.0
+    rec[:, 11] = np.arange(len(alphas)) + 1.0
+    img, tf, nc, fl = raster.render_fwd(rec, 8, 6)
+    assert nc[3, 4] == 3
+    assert img[3, 4, 0] == pytest.approx(1.0 - 1e-3, abs=1e-15)
+    assert tf[3, 4] == pytest.approx(1e-3, rel=1e-12)
+
+
+def test_opacity_clamp_golden():
+    """alpha = min(0.99, sigma) (the standard-splatting clamp the paper defers
+    to): a record with o = 1 centred on a pixel centre gives alpha = 0.99
+    there, so the pixel is 0.99 c with T = 0.01; at o = 0.5 it is 0.5 c."""
+    for o, a in ((1.0, 0.99), (0.995, 0.99), (0.5, 0.5)):
+        rec = np.zeros((1, 12))
+        rec[0, :5] = [4.5, 3.5, 0.2, 0.0, 0.2]
+        rec[0, 5] = 0.9
+        rec[0, 6] = o
+        rec[0, 7] = 4.0
+        rec[0, 8:11] = [1.0, 0.5, 0.25]
+        rec[0, 11] = 2.0
+        img, tf, nc, fl = raster.render_fwd(rec, 8, 6)
+        np.testing.assert_allclose(img[3, 4], a * np.array([1.0, 0.5, 0.25]), rtol=1e-15)
+        assert tf[3, 4] == pytest.approx(1.0 - a, rel=1e-14)
+
+
 # --------------------------------------------------------------------- binning
 def _qp_min(rec, x0, x1, y0, y1):
     """min of the record's quadratic form over a rectangle, by scipy's
@@ -593,6 +630,29 @@ def test_binning_is_exact_and_complete_brute_force():
                 if (q <= rec[i, 5]).any():
                     assert hit
     assert n_hits > 20
+
+
+@pytest.mark.parametrize("a,b,c", [(1.0, 0.0, 1.0), (2.0, 0.5, 1.0), (0.5, -0.2, 3.0)])
+def test_tile_test_threshold_golden(a, b, c):
+    """The overlap rule (tile pixel-centre rectangle, min r <= rho (1 + 2^-10))
+    at its boundary.  A record centred a distance d to the right of the
+    rectangle [0.5, 15.5]^2, level with its middle row: on the right edge
+    dx = -d is fixed and r is smallest at dy* = b d / c, where r equals
+    (a c - b^2) d^2 / c (completing the square; dy* lies on the edge here).
+    A rho just above that minimum over (1 + 2^-10) is a hit, just below it
+    a miss."""
+    d = 3.0
+    qmin = (a * c - b * b) * d * d / c
+    assert abs(b * d / c) < 7.0
+    mx, my = 15.5 + d, 8.0
+    for rel, want in ((1 + 1e-9, True), (1 - 1e-9, False)):
+        rho = qmin / (1.0 + 2.0 ** -10) * rel
+        assert raster.tile_hit(mx, my, a, b, c, rho, 0.5, 15.5, 0.5, 15.5) == want, (rel, want)
+    # the same minimum seen from below the rectangle (dy fixed, dx* = b d / a)
+    qmin_y = (a * c - b * b) * d * d / a
+    for rel, want in ((1 + 1e-9, True), (1 - 1e-9, False)):
+        rho = qmin_y / (1.0 + 2.0 ** -10) * rel
+        assert raster.tile_hit(8.0, 15.5 + d, a, b, c, rho, 0.5, 15.5, 0.5, 15.5) == want
 
 
 def test_binning_keys_sort_and_ranges():
@@ -667,11 +727,14 @@ def test_oracle_gradient_matches_finite_differences(dim, rot, dist):
     _fd_check(P, dim, rot, view, rng)
 
 
-def test_raster_adjoint_matches_finite_differences_on_records():
+@pytest.mark.parametrize("saturated", [False, True])
+def test_raster_adjoint_matches_finite_differences_on_records(saturated):
     rng = np.random.default_rng(1)
     W, H = 24, 20
     rec = make_splat_records(30, W, H, seed=4, max_extent=6.0, cull_frac=0.0).astype(np.float64)
     rec[:, 6] = rng.uniform(0.1, 0.9, size=30)
+    if saturated:   # sigma above the 0.99 clamp near the centres: alpha is flat in them
+        rec[::2, 6] = rng.uniform(0.995, 1.0, size=15)
     rec[:, 5] = 0.999
     wimg = rng.normal(size=(H, W, 3))
     wt = rng.normal(size=(H, W))
