@@ -21,8 +21,8 @@ from oracle import build as obuild
 from oracle import preprocess as pp
 from oracle import raster
 
-from . import test_oracle_pins as P
-from . import test_oracle_pins_geometry as G
+import test_oracle_pins as P
+import test_oracle_pins_geometry as G
 
 F64 = torch.float64
 
