@@ -258,6 +258,9 @@ class UBSRenderFunction(torch.autograd.Function):
         image, t_final = renderer.forward(scenes, list(views))
         ctx.renderer = renderer
         ctx.generation = renderer.generation
+        # an output the loss does not use arrives in backward as None (no
+        # zero tensor, so no transmittance term is read for it)
+        ctx.set_materialize_grads(False)
         return image, t_final
 
     @staticmethod
@@ -265,10 +268,13 @@ class UBSRenderFunction(torch.autograd.Function):
         r = ctx.renderer
         if r.generation != ctx.generation:
             raise RuntimeError("the renderer ran another frame before this backward")
-        d_image = d_image.contiguous() if d_image is not None else None
-        if d_image is None:
+        if d_image is None and d_t_final is None:
+            return (None, None, None, None) + (None,) * len(r.frame.scenes)
+        if d_image is None:   # the C call takes d_image whenever d_t_final is given
             d_image = torch.zeros((r.layout.n_pixels, 3), dtype=torch.float32, device=r.device)
-        d_t_final = d_t_final.contiguous() if d_t_final is not None else None
+        d_image = d_image.to(torch.float32).contiguous()
+        if d_t_final is not None:
+            d_t_final = d_t_final.to(torch.float32).contiguous()
         grads = r.backward(d_image, d_t_final)
         return (None, None, None, None, *grads)
 

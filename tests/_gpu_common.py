@@ -26,8 +26,12 @@ def to_dev(a: np.ndarray) -> torch.Tensor:
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def gpu_render(cfg: dict, tuning=None, *, want_grad: bool = False, d_images=None, l1: bool = False):
-    """Render every view of a workload on the GPU in one frame."""
+def gpu_render(cfg: dict, tuning=None, *, want_grad: bool = False, d_images=None, l1: bool = False,
+               d_tfinals=None, l1_targets=None):
+    """Render every view of a workload on the GPU in one frame.  Backward
+    (``want_grad``) takes ``d_images`` (and optionally ``d_tfinals``) per view,
+    or with ``l1`` the fused L1 loss against ``l1_targets`` (default: the
+    workload's targets)."""
     from paper_2510_03312_amd import Renderer, SceneRef, Tuning, split_views
     r = Renderer(tuning or Tuning())
     scenes = [SceneRef(to_dev(s.params), s.dim, s.rot) for s in cfg["scenes"]]
@@ -38,11 +42,15 @@ def gpu_render(cfg: dict, tuning=None, *, want_grad: bool = False, d_images=None
            "status": r.status(), "records": r.records().cpu().numpy()}
     if want_grad:
         if l1:
-            target = torch.cat([to_dev(t).view(-1, 3) for t in cfg["targets"]])
+            tg = cfg["targets"] if l1_targets is None else l1_targets
+            target = torch.cat([to_dev(np.asarray(t, dtype=np.float32)).view(-1, 3) for t in tg])
             grads = r.backward(l1_image=image, l1_target=target)
         else:
             d = torch.cat([to_dev(np.asarray(g, dtype=np.float32)).view(-1, 3) for g in d_images])
-            grads = r.backward(d)
+            dt = None
+            if d_tfinals is not None:
+                dt = torch.cat([to_dev(np.asarray(g, dtype=np.float32)).view(-1) for g in d_tfinals])
+            grads = r.backward(d, dt)
         torch.cuda.synchronize()
         out["dparams"] = [g.cpu().numpy() for g in grads]
         out["grad2d"] = r.grad2d().cpu().numpy()

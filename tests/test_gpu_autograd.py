@@ -1,0 +1,137 @@
+"""The differentiable render (``render`` / ``UBSRenderFunction``), the fused
+L1 image gradient and the transmittance gradient, against the fp64 oracle.
+
+Workload: the 6-D 1080p workload's distributions, reduced to 10,000
+primitives and a 200x120 view (a size with no threshold-ambiguous pixel, so
+the L1 loss needs no mask).  The L1 gradient sign(image - target) is
+ambiguous where the image sits on the target; the target is moved 2e-3 away
+from the oracle's image wherever the two are closer than 1e-3 (oracle values
+only), so both sides take the same sign.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from _gpu_common import (GRAD_BLOCKS, gpu_ready, gpu_render, grad_violations, log, oracle_view,
+                         to_dev)
+from oracle import preprocess as opp
+from synth import make_config
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ready(), reason="needs a GPU")]
+
+
+def _workload():
+    cfg = make_config("cfg2", n=10000, width=200, height=120)
+    o = oracle_view(cfg, 0)
+    assert int((o["flags"] != 0).sum()) == 0
+    t = cfg["targets"][0].astype(np.float64)
+    near = np.abs(o["image"] - t) < 1e-3
+    t = np.where(near, o["image"] + np.where(t >= o["image"], 2e-3, -2e-3), t)
+    log(f"  targets moved off the image: {int(near.sum())}")
+    return cfg, o, t.astype(np.float32)
+
+
+def _check_blocks(g, ref, noise, sc, label):
+    sl = opp.field_slices(sc.dim, sc.rot)
+    bad = 0
+    for name in GRAD_BLOCKS:
+        s = sl[name]
+        if s.stop <= s.start:
+            continue
+        v = grad_violations(g[s], ref[s], noise=noise[s])
+        strict = grad_violations(g[s], ref[s])
+        log(f"  {label} {name}: max|ref| {np.abs(ref[s]).max():.3g} strict-relative "
+            f"violations {int(strict.sum())}, with the fp32 sum budget {int(v.sum())}")
+        bad += int(v.sum())
+    return bad
+
+
+def test_fused_l1_gradient_matches_oracle():
+    log("[l1] fused L1 vs oracle")
+    cfg, _, target = _workload()
+    g = gpu_render(cfg, want_grad=True, l1=True, l1_targets=[target])
+    o = oracle_view(cfg, 0, l1_target=target.astype(np.float64))
+    sc = cfg["scenes"][0]
+    assert _check_blocks(g["dparams"][0], o["dparams"], o["dparams_noise"], sc, "fused") == 0
+
+
+@pytest.mark.parametrize("loss", ["image", "image+t_final", "t_final"])
+def test_autograd_render_matches_oracle(loss):
+    """torch.autograd.backward through ``render``: an L1 image loss, plus a
+    weighted sum of the final transmittance, or the latter alone."""
+    from paper_2510_03312_amd import Renderer
+    from paper_2510_03312_amd.renderer import render
+    log(f"[autograd] loss {loss}")
+    cfg, _, target = _workload()
+    sc, view = cfg["scenes"][0], cfg["views"][0]
+    H, W = view.height, view.width
+    rng = np.random.default_rng(17)
+    w_t = rng.normal(size=(H, W)) / math.sqrt(H * W)
+    params = to_dev(sc.params).requires_grad_(True)
+    r = Renderer()
+    image, t_final = render(r, [params], [sc.dim], [sc.rot], cfg["views"])
+    terms = []
+    if "image" in loss:
+        terms.append((image - to_dev(target).view(-1, 3)).abs().mean())
+    if "t_final" in loss:
+        terms.append((t_final * to_dev(w_t.astype(np.float32)).view(-1)).sum())
+    torch.autograd.backward(sum(terms))
+    torch.cuda.synchronize()
+    g = params.grad.cpu().numpy()
+    d_image = (np.sign(image.detach().cpu().numpy().reshape(H, W, 3) - target) / (3.0 * H * W)
+               if "image" in loss else np.zeros((H, W, 3)))
+    o_img = oracle_view(cfg, 0)["image"]
+    # the sign taken on the GPU's image is the oracle's sign (targets moved off)
+    assert np.array_equal(np.sign(d_image), np.sign(o_img - target) * ("image" in loss))
+    d_t = w_t.astype(np.float32).astype(np.float64) if "t_final" in loss else None
+    o = oracle_view(cfg, 0, d_image=d_image, d_tfinal=d_t)
+    assert _check_blocks(g, o["dparams"], o["dparams_noise"], sc, loss) == 0
+
+
+def test_autograd_gradient_equals_renderer_backward():
+    """The Function hands the same d_image / d_t_final to the C call as a
+    direct ``Renderer.backward``; the atomics' order aside, same gradients."""
+    from paper_2510_03312_amd import Renderer, SceneRef
+    from paper_2510_03312_amd.renderer import render
+    log("[autograd] vs Renderer.backward")
+    cfg = make_config("headline", n=20000, width=160, height=96)
+    sc = cfg["scenes"][0]
+    params = to_dev(sc.params).requires_grad_(True)
+    image, t_final = render(Renderer(), [params], [sc.dim], [sc.rot], cfg["views"])
+    rng = np.random.default_rng(5)
+    wi = to_dev(rng.normal(size=(160 * 96, 3)).astype(np.float32))
+    wt = to_dev(rng.normal(size=(160 * 96,)).astype(np.float32))
+    torch.autograd.backward([image, t_final], [wi, wt])
+    r2 = Renderer()
+    r2.forward([SceneRef(to_dev(sc.params), sc.dim, sc.rot)], cfg["views"])
+    (g2,) = r2.backward(wi, wt)
+    torch.cuda.synchronize()
+    v = grad_violations(params.grad.cpu().numpy(), g2.cpu().numpy().astype(np.float64),
+                        rtol=1e-4, floor=1e-3)
+    assert v.sum() == 0
+
+
+def test_autograd_multi_scene_frame():
+    """Two scenes in one differentiable frame: each parameter tensor gets the
+    gradient of its own scene (checked against one frame per scene)."""
+    from paper_2510_03312_amd import Renderer
+    from paper_2510_03312_amd.renderer import render
+    log("[autograd] two scenes")
+    cfg = make_config("cfg4", scene_sizes=(3000, 5000), n_views=4)
+    for v in cfg["views"]:
+        v.width, v.height, v.cx, v.cy = 96, 64, 48.0, 32.0
+        v.fx = v.fy = float(np.float32(48.0 / math.tan(math.radians(30))))
+    ps = [to_dev(s.params).requires_grad_(True) for s in cfg["scenes"]]
+    image, _ = render(Renderer(), ps, [s.dim for s in cfg["scenes"]],
+                      [s.rot for s in cfg["scenes"]], cfg["views"])
+    w = np.full((96 * 64 * 4, 3), 1e-3, np.float32)
+    torch.autograd.backward(image, to_dev(w))
+    for k, sc in enumerate(cfg["scenes"]):
+        views = [v for v in cfg["views"] if v.scene == k]
+        one = {"scenes": cfg["scenes"], "views": views, "targets": []}
+        ref = gpu_render(one, want_grad=True, d_images=[np.full((64, 96, 3), 1e-3)] * len(views))
+        v = grad_violations(ps[k].grad.cpu().numpy(), ref["dparams"][k].astype(np.float64),
+                            rtol=1e-4, floor=1e-3)
+        assert v.sum() == 0, k

@@ -19,7 +19,7 @@ def _grads_close(a, b):
 
 
 @pytest.mark.parametrize("tile", [(16, 16), (16, 8), (8, 8), (32, 16)])
-@pytest.mark.parametrize("batch", [64, 256])
+@pytest.mark.parametrize("batch", [64, 128, 256])
 @pytest.mark.parametrize("persistent", [False, True])
 def test_tuning_variants_render_identically(tile, batch, persistent):
     from paper_2510_03312_amd import UBS_TUNE_PERSISTENT, Tuning

@@ -244,18 +244,26 @@ def _block_slices(dim, rot):
     return {k: sl[k] for k in GRAD_BLOCKS if sl[k].stop > sl[k].start}
 
 
+@pytest.mark.parametrize("with_dt", [False, True])
 @pytest.mark.parametrize("case", ["cfg0_3d_quat", "cfg0_3d_skew_ragged", "cfg1_6d_ragged",
                                   "cfg1_6d_skew", "headline_7d_ragged"])
-def test_gradients_match_oracle(case):
-    log(f"[bwd] {case}")
+def test_gradients_match_oracle(case, with_dt):
+    """d loss / d params for a seeded d_image (and, with_dt, a seeded
+    d loss / d T_final: the adjoint of the final transmittance) against the
+    oracle's fp64 adjoint."""
+    log(f"[bwd] {case} d_t_final={with_dt}")
     cfg = _cfg(case)
     view = cfg["views"][0]
     o0 = oracle_view(cfg, 0)
     rng = np.random.default_rng(3)
     ok = (o0["flags"] == 0)
     dimg = rng.normal(size=(view.height, view.width, 3)) * ok[..., None] / math.sqrt(ok.size)
-    o = oracle_view(cfg, 0, d_image=dimg)
-    g = gpu_render(cfg, want_grad=True, d_images=[dimg])
+    dtf = None
+    if with_dt:
+        dtf = (rng.normal(size=(view.height, view.width)) * ok / math.sqrt(ok.size))
+        dtf = dtf.astype(np.float32).astype(np.float64)
+    o = oracle_view(cfg, 0, d_image=dimg, d_tfinal=dtf)
+    g = gpu_render(cfg, want_grad=True, d_images=[dimg], d_tfinals=None if dtf is None else [dtf])
     sc = cfg["scenes"][0]
     total_bad = 0
     for name, s in _block_slices(sc.dim, sc.rot).items():
@@ -279,9 +287,11 @@ def test_fused_l1_gradient_equals_explicit():
     np.testing.assert_allclose(a["dparams"][0], b["dparams"][0], rtol=1e-5, atol=1e-12)
 
 
-def test_gradients_match_finite_differences_on_subscene():
-    """64 primitives, 32x32 crop at the centre of the 1920x1080 6-D workload."""
-    log("[bwd] FD sub-scene")
+@pytest.mark.parametrize("with_dt", [False, True])
+def test_gradients_match_finite_differences_on_subscene(with_dt):
+    """64 primitives, 32x32 crop at the centre of the 1920x1080 6-D workload;
+    the loss is <w, image> (+ <w_t, T_final> with_dt)."""
+    log(f"[bwd] FD sub-scene d_t_final={with_dt}")
     full = make_config("cfg2", n=200_000)
     sc = full["scenes"][0]
     view = full["views"][0]
@@ -304,8 +314,11 @@ def test_gradients_match_finite_differences_on_subscene():
     rng = np.random.default_rng(9)
     o0 = oracle_view(cfg, 0)
     wimg = rng.normal(size=(32, 32, 3)) * (o0["flags"] == 0)[..., None]
-    o = oracle_view(cfg, 0, d_image=wimg)
-    g = gpu_render(cfg, want_grad=True, d_images=[wimg])
+    wt = None
+    if with_dt:
+        wt = (rng.normal(size=(32, 32)) * (o0["flags"] == 0)).astype(np.float32).astype(np.float64)
+    o = oracle_view(cfg, 0, d_image=wimg, d_tfinal=wt)
+    g = gpu_render(cfg, want_grad=True, d_images=[wimg], d_tfinals=None if wt is None else [wt])
     from oracle import render as orender
     P64 = sub.astype(np.float64)
     scale = np.abs(o["dparams"]).max()
@@ -318,8 +331,8 @@ def test_gradients_match_finite_differences_on_subscene():
                 Pp, Pm = P64.copy(), P64.copy()
                 Pp[f, i] += hh
                 Pm[f, i] -= hh
-                fd.append((orender.loss_value(Pp, sc.dim, sc.rot, crop, wimg)
-                           - orender.loss_value(Pm, sc.dim, sc.rot, crop, wimg)) / (2 * hh))
+                fd.append((orender.loss_value(Pp, sc.dim, sc.rot, crop, wimg, wt)
+                           - orender.loss_value(Pm, sc.dim, sc.rot, crop, wimg, wt)) / (2 * hh))
             if abs(fd[0] - fd[1]) > 1e-6 * max(abs(fd[1]), 1e-3 * scale):
                 continue
             gv = float(g["dparams"][0][f, i])
