@@ -376,6 +376,26 @@ ubs_status ubs_relocate(int32_t dim, int32_t rot, int64_t n, float* params, floa
                         void* stream);
 
 /*
+ * ubs_relocate_noalloc -- ubs_relocate without a workspace argument and
+ * without any device allocation, for callers that cannot allocate: code
+ * under HIP graph capture, tight serving or training loops, harnesses that
+ * forbid hipMalloc.  Same arguments, semantics and results as ubs_relocate
+ * (minus ws, ws_bytes, ws_bytes_needed).  The workspace is a static device
+ * array inside the library of the size ubs_relocate needs for
+ * UBS_RELOCATE_NOALLOC_MAX_N primitives (about 64 MiB), one per GPU, held
+ * until the process ends; its address is looked up on the first call on
+ * each device (the device current at the call).  Every call on a GPU uses
+ * that GPU's one array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and give wrong results; serialise them.
+ * Errors: as ubs_relocate, plus UBS_ERR_CAPACITY for n >
+ * UBS_RELOCATE_NOALLOC_MAX_N (before any launch).
+ */
+#define UBS_RELOCATE_NOALLOC_MAX_N (1 << 21)
+ubs_status ubs_relocate_noalloc(int32_t dim, int32_t rot, int64_t n, float* params, float* m,
+                                float* v, const double* uniforms, float o_min,
+                                uint32_t* targets_out, uint64_t* n_dead_out, void* stream);
+
+/*
  * ubs_ssim_loss -- the image loss of Section 4.5, (1 - lambda_ssim) L1 +
  * lambda_ssim (1 - SSIM), and its gradient with respect to the image.
  * SSIM (the measure the paper cites) per pixel and channel under an 11 x 11

@@ -27,10 +27,11 @@ UBS_TUNE_PERSISTENT = 1
 UBS_TUNE_PRE_FP32 = 2
 UBS_TUNE_NO_BETA_COND = 4
 UBS_TUNE_NO_BETA_OPACITY = 8
+UBS_RELOCATE_NOALLOC_MAX_N = 1 << 21
 
 EXPORTS = ("ubs_preprocess", "ubs_bin_sort", "ubs_render_fwd", "ubs_render_bwd",
-           "ubs_adam_step", "ubs_relocate", "ubs_ssim_loss", "ubs_param_count",
-           "ubs_abi_version")
+           "ubs_adam_step", "ubs_relocate", "ubs_relocate_noalloc", "ubs_ssim_loss",
+           "ubs_param_count", "ubs_abi_version")
 
 
 class UbsScene(ctypes.Structure):
@@ -114,6 +115,10 @@ def load() -> ctypes.CDLL:
                                    c_void_p, c_float, c_void_p, c_uint64, POINTER(c_uint64),
                                    c_void_p, c_void_p, c_void_p]
         L.ubs_relocate.restype = c_int32
+        L.ubs_relocate_noalloc.argtypes = [c_int32, c_int32, c_int64, c_void_p, c_void_p,
+                                           c_void_p, c_void_p, c_float, c_void_p, c_void_p,
+                                           c_void_p]
+        L.ubs_relocate_noalloc.restype = c_int32
         L.ubs_ssim_loss.argtypes = [c_int32, POINTER(c_int32), c_void_p, c_void_p, c_float,
                                     c_void_p, c_void_p, c_void_p, c_uint64, POINTER(c_uint64),
                                     c_void_p]
@@ -176,6 +181,14 @@ def ubs_relocate(dim: int, rot: int, n: int, params: int, m: int, v: int, unifor
     if check:
         _check("ubs_relocate", code)
     return int(need.value) if not ws else code
+
+
+def ubs_relocate_noalloc(dim: int, rot: int, n: int, params: int, m: int, v: int, uniforms: int,
+                         o_min: float, targets_out: int, n_dead_out: int, stream: int,
+                         check: bool = True) -> int:
+    code = load().ubs_relocate_noalloc(dim, rot, n, params, m, v, uniforms, o_min,
+                                       targets_out or None, n_dead_out or None, stream or None)
+    return _check("ubs_relocate_noalloc", code) if check else code
 
 
 def ubs_ssim_loss(sizes, image: int, target: int, lambda_ssim: float, d_image: int, loss: int,

@@ -16,6 +16,7 @@
 //   apply     row by row: a dead primitive takes its pick's row (or o'), a
 //             picked one gets o', the moments of both are zeroed
 #include <cmath>
+#include <mutex>
 
 #include "ubs_internal.hpp"
 
@@ -34,27 +35,33 @@ struct RelocLayout {
   uint32_t n_tiles;
 };
 
-static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+constexpr uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
-static RelocLayout reloc_layout(int64_t n) {
+constexpr RelocLayout reloc_layout(int64_t n) {
   RelocLayout L{};
   const uint64_t un = uint64_t(n);
   L.n_tiles = uint32_t((un + kRelTile - 1) / kRelTile);
   uint64_t off = 0;
-  auto take = [&](uint64_t b) { const uint64_t o = off; off = align256(off + b); return o; };
-  L.cdf = take(8 * un);
-  L.o_keep = take(4 * un);
-  L.dead = take(4 * un);
-  L.offs = take(4 * un);
-  L.list = take(4 * un);
-  L.targets = take(4 * un);
-  L.counts = take(4 * un);
-  L.sums_u32 = take(4 * (uint64_t(L.n_tiles) + 1));
-  L.sums_f64 = take(8 * (uint64_t(L.n_tiles) + 1));
-  L.n_dead = take(8);
+  L.cdf = off;      off = align256(off + 8 * un);
+  L.o_keep = off;   off = align256(off + 4 * un);
+  L.dead = off;     off = align256(off + 4 * un);
+  L.offs = off;     off = align256(off + 4 * un);
+  L.list = off;     off = align256(off + 4 * un);
+  L.targets = off;  off = align256(off + 4 * un);
+  L.counts = off;   off = align256(off + 4 * un);
+  L.sums_u32 = off; off = align256(off + 4 * (uint64_t(L.n_tiles) + 1));
+  L.sums_f64 = off; off = align256(off + 8 * (uint64_t(L.n_tiles) + 1));
+  L.n_dead = off;   off = align256(off + 8);
   L.bytes = off;
   return L;
 }
+
+// Workspace of ubs_relocate_noalloc: a relocation of up to
+// UBS_RELOCATE_NOALLOC_MAX_N primitives, one copy per GPU, kept for the
+// life of the process.  Every word a call reads is first written by that
+// call (weights, counts, scans), so nothing needs clearing between calls.
+constexpr uint64_t kNoallocBytes = reloc_layout(UBS_RELOCATE_NOALLOC_MAX_N).bytes;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
 
 __global__ void __launch_bounds__(kRelThreads) reloc_weights_kernel(
     const float* __restrict__ params, int64_t n, int F, int o_row, float o_min,
@@ -205,31 +212,41 @@ __global__ void __launch_bounds__(kRelThreads) reloc_apply_kernel(
   }
 }
 
-}  // namespace ubs
+// Device address of `scratch` on the current device, looked up once per
+// device (each GPU holds its own copy of the array at its own address).
+static ubs_status noalloc_scratch(char** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptr[kMaxDevices] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return UBS_ERR_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return UBS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return UBS_ERR_HIP;
+    ptr[dev] = p;
+  }
+  *out = static_cast<char*>(ptr[dev]);
+  return UBS_OK;
+}
 
-using namespace ubs;
-
-extern "C" ubs_status ubs_relocate(int32_t dim, int32_t rot, int64_t n, float* params, float* m,
-                                   float* v, const double* uniforms, float o_min, void* ws,
-                                   uint64_t ws_bytes, uint64_t* ws_bytes_needed,
-                                   uint32_t* targets_out, uint64_t* n_dead_out, void* stream) {
+static ubs_status relocate_args(int32_t dim, int32_t rot, int64_t n, float o_min) {
   if (dim < 3 || dim > kMaxDim || (rot != UBS_ROT_QUAT && rot != UBS_ROT_SKEW) || n < 0)
     return UBS_ERR_ARG;
   if (!dim_ok(dim)) return UBS_ERR_UNSUPPORTED;
   if (n > (int64_t(1) << 31) - 1) return UBS_ERR_UNSUPPORTED;
   if (!(o_min >= 0.0f)) return UBS_ERR_ARG;
-  const RelocLayout L = reloc_layout(n);
-  if (!ws) {
-    if (!ws_bytes_needed) return UBS_ERR_ARG;
-    *ws_bytes_needed = L.bytes;
-    return UBS_OK;
-  }
-  if (ws_bytes < L.bytes) return UBS_ERR_CAPACITY;
-  if (n == 0) return UBS_OK;
-  if (!params || !m || !v || !uniforms) return UBS_ERR_ARG;
+  return UBS_OK;
+}
+
+// The relocation's launches over a workspace at `base` laid out by L.
+static ubs_status relocate_run(int32_t dim, int32_t rot, int64_t n, float* params, float* m,
+                               float* v, const double* uniforms, float o_min, char* base,
+                               const RelocLayout& L, uint32_t* targets_out,
+                               uint64_t* n_dead_out, void* stream) {
   const ParamRows pr = param_rows(dim - 3, rot);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  char* base = static_cast<char*>(ws);
   double* cdf = reinterpret_cast<double*>(base + L.cdf);
   float* o_keep = reinterpret_cast<float*>(base + L.o_keep);
   uint32_t* dead = reinterpret_cast<uint32_t*>(base + L.dead);
@@ -255,4 +272,43 @@ extern "C" ubs_status ubs_relocate(int32_t dim, int32_t rot, int64_t n, float* p
   if (n_dead_out)
     hipLaunchKernelGGL(copy_count_kernel, dim3(1), dim3(64), 0, st, n_dead, n_dead_out);
   return hipGetLastError() == hipSuccess ? UBS_OK : UBS_ERR_HIP;
+}
+
+}  // namespace ubs
+
+using namespace ubs;
+
+extern "C" ubs_status ubs_relocate(int32_t dim, int32_t rot, int64_t n, float* params, float* m,
+                                   float* v, const double* uniforms, float o_min, void* ws,
+                                   uint64_t ws_bytes, uint64_t* ws_bytes_needed,
+                                   uint32_t* targets_out, uint64_t* n_dead_out, void* stream) {
+  const ubs_status a = relocate_args(dim, rot, n, o_min);
+  if (a != UBS_OK) return a;
+  const RelocLayout L = reloc_layout(n);
+  if (!ws) {
+    if (!ws_bytes_needed) return UBS_ERR_ARG;
+    *ws_bytes_needed = L.bytes;
+    return UBS_OK;
+  }
+  if (ws_bytes < L.bytes) return UBS_ERR_CAPACITY;
+  if (n == 0) return UBS_OK;
+  if (!params || !m || !v || !uniforms) return UBS_ERR_ARG;
+  return relocate_run(dim, rot, n, params, m, v, uniforms, o_min, static_cast<char*>(ws), L,
+                      targets_out, n_dead_out, stream);
+}
+
+extern "C" ubs_status ubs_relocate_noalloc(int32_t dim, int32_t rot, int64_t n, float* params,
+                                           float* m, float* v, const double* uniforms,
+                                           float o_min, uint32_t* targets_out,
+                                           uint64_t* n_dead_out, void* stream) {
+  const ubs_status a = relocate_args(dim, rot, n, o_min);
+  if (a != UBS_OK) return a;
+  if (n > UBS_RELOCATE_NOALLOC_MAX_N) return UBS_ERR_CAPACITY;
+  if (n == 0) return UBS_OK;
+  if (!params || !m || !v || !uniforms) return UBS_ERR_ARG;
+  char* base = nullptr;
+  const ubs_status sc = noalloc_scratch(&base);
+  if (sc != UBS_OK) return sc;
+  return relocate_run(dim, rot, n, params, m, v, uniforms, o_min, base, reloc_layout(n),
+                      targets_out, n_dead_out, stream);
 }

@@ -244,3 +244,23 @@ def test_ssim_loss_size_query_and_errors():
         got = _lib.ubs_ssim_loss(a["sizes"], a["image"], 0x2000, a["lam"], 0x3000, 0, 0x4000,
                                  a["ws_bytes"], 0, check=False)
         assert got == code, change
+
+
+def test_python_constants_match_the_header():
+    src = open(HEADER).read()
+    defs = dict(re.findall(r"^#define\s+(UBS_\w+)\s+(.+?)\s*(?:/\*.*)?$", src, re.M))
+    for name in ("UBS_TUNE_PERSISTENT", "UBS_TUNE_PRE_FP32", "UBS_TUNE_NO_BETA_COND",
+                 "UBS_TUNE_NO_BETA_OPACITY", "UBS_RELOCATE_NOALLOC_MAX_N"):
+        assert eval(defs[name].replace("u", "")) == getattr(_lib, name), name
+
+
+def test_noalloc_relocate_rejects_oversize_before_any_launch():
+    big = _lib.UBS_RELOCATE_NOALLOC_MAX_N + 1
+    assert _lib.ubs_relocate_noalloc(7, 0, big, 0, 0, 0, 0, 0.005, 0, 0, 0,
+                                     check=False) == _lib.UBS_ERR_CAPACITY
+    assert _lib.ubs_relocate_noalloc(5, 0, 10, 0, 0, 0, 0, 0.005, 0, 0, 0,
+                                     check=False) == _lib.UBS_ERR_UNSUPPORTED
+    assert _lib.ubs_relocate_noalloc(7, 0, 10, 0, 0, 0, 0, 0.005, 0, 0, 0,
+                                     check=False) == _lib.UBS_ERR_ARG
+    assert _lib.ubs_relocate_noalloc(7, 0, 0, 0, 0, 0, 0, 0.005, 0, 0, 0,
+                                     check=False) == _lib.UBS_OK
