@@ -334,4 +334,4 @@ def preprocess(params: torch.Tensor, dim: int, rot: int, view,
     rec = torch.where(valid[:, None], rec, zero)
     return {"rec": rec, "valid": valid, "Sigma": Sigma, "L": L, "q": q, "v": v,
             "o_q": o_q, "mu_c": mu_c, "S_c": S_c, "Sp": Sp, "depth": depth,
-            "mean2d": mean2d}
+            "mean2d": mean2d, "beta_x": beta_x}

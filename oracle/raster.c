@@ -29,7 +29,12 @@
  *   2  T (1 - alpha) lies within a relative band of 1e-4
  *   4  two consecutive contributors have depths within a relative band
  *   8  sigma lies within a relative band of the 0.99 clamp
- *   16 an "ambiguous" record (validity uncertain) covers the pixel
+ *   16 an "ambiguous" record (validity uncertain) may reach the pixel
+ * amb[i] (when given) marks such records: 1 = its culling (near plane,
+ * definiteness) is uncertain, so it may reach its whole support r < 1;
+ * 2 = only o(q) >= 1/255 is uncertain (o(q) within band_opacity of it), so
+ * it can add a contribution only where alpha may reach 1/255, i.e. at
+ * r <= max(rho, 1 - (1 + band_opacity)^(-1/beta)).
  */
 #include <math.h>
 #include <stdint.h>
@@ -41,7 +46,7 @@
 #define T_STOP 1e-4
 
 typedef struct {
-    double band_alpha, band_t, band_depth, band_clamp;
+    double band_alpha, band_t, band_depth, band_clamp, band_opacity;
 } bands_t;
 
 static const double *g_depth;
@@ -163,7 +168,12 @@ static int shade_pixel(const double *rec, const unsigned char *amb, const rows_t
         double dx = px - r[0], dy = py - r[1];
         double q = r[2] * dx * dx + 2.0 * r[3] * dx * dy + r[4] * dy * dy;
         if (amb && amb[id]) {
-            if (q < 1.0) fl |= 16;
+            double reach = 1.0;
+            if (amb[id] == 2) {
+                reach = 1.0 - pow(1.0 + bd->band_opacity, -1.0 / r[7]);
+                if (r[5] > reach) reach = r[5];
+            }
+            if (q < reach) fl |= 16;
             if (!(r[5] > 0.0)) continue;
         }
         double rho = r[5];
@@ -205,10 +215,10 @@ static int shade_pixel(const double *rec, const unsigned char *amb, const rows_t
  * Pixels are restricted to rows [y_begin, y_end) (the rest is untouched).
  */
 int oracle_render_fwd(int n, const double *rec, const unsigned char *amb, int W, int H,
-                      int y_begin, int y_end, const double *bands4, double *image, double *tfinal,
+                      int y_begin, int y_end, const double *bands5, double *image, double *tfinal,
                       int *ncontrib, unsigned *flags)
 {
-    bands_t bd = {bands4[0], bands4[1], bands4[2], bands4[3]};
+    bands_t bd = {bands5[0], bands5[1], bands5[2], bands5[3], bands5[4]};
     rows_t R;
     build_rows(n, rec, amb, H, &R);
     for (int y = y_begin; y < y_end; ++y)
@@ -230,10 +240,10 @@ int oracle_render_fwd(int n, const double *rec, const unsigned char *amb, int W,
 
 /* Forward values at an explicit list of pixels (xs, ys), for sampled checks. */
 int oracle_render_pixels(int n, const double *rec, const unsigned char *amb, int W, int H,
-                         int npix, const int *xs, const int *ys, const double *bands4,
+                         int npix, const int *xs, const int *ys, const double *bands5,
                          double *color, double *tfinal, int *ncontrib, unsigned *flags)
 {
-    bands_t bd = {bands4[0], bands4[1], bands4[2], bands4[3]};
+    bands_t bd = {bands5[0], bands5[1], bands5[2], bands5[3], bands5[4]};
     rows_t R;
     build_rows(n, rec, amb, H, &R);
     for (int i = 0; i < npix; ++i) {
@@ -271,7 +281,7 @@ int oracle_render_bwd(int n, const double *rec, int W, int H, int y_begin, int y
                       const double *d_image, const double *d_tfinal, double *d_rec,
                       double *d_rec_abs)
 {
-    bands_t bd = {1e-300, 1e-300, 1e-300, 1e-300};
+    bands_t bd = {1e-300, 1e-300, 1e-300, 1e-300, 1e-300};
     rows_t R;
     build_rows(n, rec, NULL, H, &R);
     int cap = R.m > 0 ? R.m : 1;
@@ -376,6 +386,49 @@ static int tile_hit(double mx, double my, double a, double b, double c, double r
  * | bits(depth as float32); value = rec_base + index.  Writes at most cap
  * pairs; returns the total number of pairs.
  */
+/* Tiles worth testing for a record: those whose pixel-centre rectangle
+ * meets the bounding box of the ellipse {r <= rho (1 + 2^-10)}, widened by
+ * a millionth and a pixel (far more than the rounding of the tile test).
+ * Pure speed: the products of the float32 conic entries are exact in
+ * float64, so the determinant is accurate however elongated the ellipse;
+ * a conic that is not positive definite, or any doubt, scans every tile.
+ * g_bin_prefilter = 0 scans every tile of every record (the pins compare
+ * the two). */
+static int g_bin_prefilter = 1;
+void oracle_set_bin_prefilter(int on) { g_bin_prefilter = on; }
+
+static void tile_window(const float *r, int W, int H, int tw, int th, int tx_n, int ty_n,
+                        int *tx_lo, int *tx_hi, int *ty_lo, int *ty_hi)
+{
+    *tx_lo = 0; *tx_hi = tx_n - 1; *ty_lo = 0; *ty_hi = ty_n - 1;
+    if (!g_bin_prefilter) return;
+    double a = (double)r[2], b = (double)r[3], c = (double)r[4];
+    double det = a * c - b * b;
+    if (!(det > 0.0) || !(a > 0.0) || !(c > 0.0)) return;
+    double lim = (double)r[5] * (1.0 + 0x1p-10);
+    double hx = sqrt(lim * c / det) * (1.0 + 1e-6) + 1.0;
+    double hy = sqrt(lim * a / det) * (1.0 + 1e-6) + 1.0;
+    double xmin = (double)r[0] - hx, xmax = (double)r[0] + hx;
+    double ymin = (double)r[1] - hy, ymax = (double)r[1] + hy;
+    if (!(xmax >= 0.0) || !(ymax >= 0.0) || !(xmin <= (double)W) || !(ymin <= (double)H)) {
+        *tx_lo = 1; *tx_hi = 0;   /* no tile */
+        return;
+    }
+    /* clip to the view (keeps the int conversions in range) */
+    if (xmin < 0.0) xmin = 0.0;
+    if (ymin < 0.0) ymin = 0.0;
+    if (xmax > (double)W) xmax = (double)W;
+    if (ymax > (double)H) ymax = (double)H;
+    /* tile tx spans pixel centres [tx tw + 0.5, tx tw + tw - 0.5] */
+    int lo = (int)floor((xmin - 0.5) / tw) - 1, hi = (int)floor((xmax - 0.5) / tw) + 1;
+    if (lo > *tx_lo) *tx_lo = lo;
+    if (hi < *tx_hi) *tx_hi = hi;
+    lo = (int)floor((ymin - 0.5) / th) - 1;
+    hi = (int)floor((ymax - 0.5) / th) + 1;
+    if (lo > *ty_lo) *ty_lo = lo;
+    if (hi < *ty_hi) *ty_hi = hi;
+}
+
 int64_t oracle_bin(int n, const float *rec32, int W, int H, int tw, int th, uint32_t tile_base,
                    uint32_t rec_base, int64_t cap, uint64_t *keys, uint32_t *vals)
 {
@@ -386,8 +439,10 @@ int64_t oracle_bin(int n, const float *rec32, int W, int H, int tw, int th, uint
         if (!(r[5] > 0.0f)) continue;
         uint32_t dbits;
         memcpy(&dbits, &r[11], 4);
-        for (int ty = 0; ty < ty_n; ++ty)
-            for (int tx = 0; tx < tx_n; ++tx) {
+        int tx_lo, tx_hi, ty_lo, ty_hi;
+        tile_window(r, W, H, tw, th, tx_n, ty_n, &tx_lo, &tx_hi, &ty_lo, &ty_hi);
+        for (int ty = ty_lo; ty <= ty_hi; ++ty)
+            for (int tx = tx_lo; tx <= tx_hi; ++tx) {
                 int px1 = tx * tw + tw - 1, py1 = ty * th + th - 1;
                 if (px1 > W - 1) px1 = W - 1;
                 if (py1 > H - 1) py1 = H - 1;

@@ -15,8 +15,12 @@ from . import build as _build
 _lib = None
 
 # relative bands for the ambiguity flags (alpha/r thresholds, T stop, depth
-# order, 0.99 clamp); see raster.c
-DEFAULT_BANDS = (1e-4, 1e-4, 1e-5, 1e-4)
+# order, 0.99 clamp, o(q) against 1/255 of an ambiguous record); see raster.c.
+# A float32 renderer evaluates sigma = o (1 - r)^beta to ~1e-6 relative
+# (exp2/log2 of an exponent of magnitude up to ~8), T over tens of factors to
+# a few 1e-6, o(q) to a few 1e-7, and rounds depths to float32 (6e-8):
+# the bands are about ten times those.
+DEFAULT_BANDS = (1e-5, 1e-5, 1e-6, 1e-5, 1e-5)
 
 _D = ctypes.POINTER(ctypes.c_double)
 _F = ctypes.POINTER(ctypes.c_float)
@@ -52,6 +56,8 @@ def load(path: str):
                              _U64, _U32]
     L.oracle_tile_hit.argtypes = [ctypes.c_double] * 10
     L.oracle_tile_hit.restype = ctypes.c_int
+    L.oracle_set_bin_prefilter.argtypes = [ctypes.c_int]
+    L.oracle_set_bin_prefilter.restype = None
     return L
 
 
@@ -122,17 +128,24 @@ def tile_hit(mx, my, a, b, c, rho, x0, x1, y0, y1) -> bool:
 
 
 def bin_view(rec32: np.ndarray, W: int, H: int, tile_w: int = 16, tile_h: int = 16,
-             tile_base: int = 0, rec_base: int = 0):
+             tile_base: int = 0, rec_base: int = 0, full_scan: bool = False):
     """Binning reference for one view: keys (uint64) and values (uint32) in
-    emission order (record index, then tiles row-major)."""
+    emission order (record index, then tiles row-major).  Each record's
+    tiles are tested inside a float64 bounding window of its ellipse; with
+    ``full_scan`` every tile of the view is tested (same result, slower)."""
     rec32 = np.ascontiguousarray(rec32, dtype=np.float32)
     n = rec32.shape[0]
-    total = lib().oracle_bin(n, _p(rec32, _F), W, H, tile_w, tile_h, tile_base, rec_base, 0,
+    L = lib()
+    L.oracle_set_bin_prefilter(0 if full_scan else 1)
+    try:
+        total = L.oracle_bin(n, _p(rec32, _F), W, H, tile_w, tile_h, tile_base, rec_base, 0,
                              None, None)
-    keys = np.zeros(max(total, 1), dtype=np.uint64)
-    vals = np.zeros(max(total, 1), dtype=np.uint32)
-    lib().oracle_bin(n, _p(rec32, _F), W, H, tile_w, tile_h, tile_base, rec_base, total,
+        keys = np.zeros(max(total, 1), dtype=np.uint64)
+        vals = np.zeros(max(total, 1), dtype=np.uint32)
+        L.oracle_bin(n, _p(rec32, _F), W, H, tile_w, tile_h, tile_base, rec_base, total,
                      _p(keys, _U64), _p(vals, _U32))
+    finally:
+        L.oracle_set_bin_prefilter(1)
     return keys[:total], vals[:total]
 
 

@@ -18,7 +18,7 @@ from . import raster
 
 # relative bands for per-primitive decisions that fp32 may take differently
 BAND_NEAR = 1e-5     # depth vs the near plane
-BAND_OPACITY = 1e-4  # o(q) vs 1/255
+BAND_OPACITY = raster.DEFAULT_BANDS[4]  # o(q) vs 1/255
 BAND_DET = 1e-6      # det(Sigma') / (Sigma'_00 Sigma'_11) vs 0
 
 # record columns that receive a compositing gradient (d_rec order)
@@ -36,6 +36,21 @@ def ambiguous_records(out: dict) -> np.ndarray:
     amb |= (np.abs(o_q * 255.0 - 1.0) <= BAND_OPACITY)
     amb |= (np.abs(det) / scale <= BAND_DET) & (depth > pp.NEAR_PLANE)
     return amb
+
+
+def ambiguity_kinds(out: dict) -> np.ndarray:
+    """uint8 per primitive for the compositing's flags: 0 unambiguous, 1 its
+    culling by geometry (near plane, definiteness) is uncertain, 2 only
+    o(q) against 1/255 is (see raster.c)."""
+    depth = out["depth"].detach().numpy()
+    Sp = out["Sp"].detach().numpy()
+    det = Sp[:, 0, 0] * Sp[:, 1, 1] - Sp[:, 0, 1] * Sp[:, 1, 0]
+    scale = np.abs(Sp[:, 0, 0] * Sp[:, 1, 1]) + 1e-300
+    geo = (np.abs(depth - pp.NEAR_PLANE) <= BAND_NEAR * pp.NEAR_PLANE)
+    geo |= (np.abs(det) / scale <= BAND_DET) & (depth > pp.NEAR_PLANE)
+    kind = np.where(ambiguous_records(out), 2, 0).astype(np.uint8)
+    kind[geo] = 1
+    return kind
 
 
 def _amb_records(out: dict, amb: np.ndarray, rec: np.ndarray) -> np.ndarray:
@@ -56,6 +71,7 @@ def _amb_records(out: dict, amb: np.ndarray, rec: np.ndarray) -> np.ndarray:
         rec[idx, 3] = np.where(ok, -Sp[:, 0, 1] / dets, 0.0)
         rec[idx, 4] = np.where(ok, Sp[:, 0, 0] / dets, 0.0)
         rec[idx, 5] = 0.0
+        rec[idx, 7] = out["beta_x"].detach().numpy()[idx]   # the reach of its flags
     return rec
 
 
@@ -85,7 +101,7 @@ def render(params: np.ndarray, dim: int, rot: int, view, *, d_image: Optional[np
     amb = ambiguous_records(out)
     rec_f = _amb_records(out, amb, rec) if amb.any() else rec
     W, H = view.width, view.height
-    img, tf, nc, fl = raster.render_fwd(rec_f, W, H, amb=amb if amb.any() else None,
+    img, tf, nc, fl = raster.render_fwd(rec_f, W, H, amb=ambiguity_kinds(out) if amb.any() else None,
                                         rows=rows, bands=bands)
     res = {"image": img, "t_final": tf, "ncontrib": nc, "flags": fl, "rec": rec,
            "valid": out["valid"].numpy(), "amb": amb, "out": out}

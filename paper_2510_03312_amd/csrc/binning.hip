@@ -10,6 +10,7 @@
 // The test is evaluated in float64, round-to-nearest, with no contraction
 // and in a fixed operation order, so that the decision is reproducible
 // bit for bit by any IEEE-754 implementation of the same expression.
+#include "tile_box.hpp"
 #include "ubs_internal.hpp"
 
 namespace ubs {
@@ -64,28 +65,10 @@ __device__ __forceinline__ int view_of_record(const DevView* __restrict__ views,
   return lo;
 }
 
-struct TileBox {
-  int tx0, tx1, ty0, ty1;  // inclusive; empty if tx0 > tx1
-};
-
-// Conservative tile bounding box of {r <= rho (1 + 2^-10)}, padded by 2 px.
+// Conservative tile box of {r <= rho (1 + 2^-10)} (tile_box.hpp).
 __device__ __forceinline__ TileBox record_tile_box(const float4 r0, const float4 r1,
                                                    const DevView& V) {
-  TileBox bx{1, 0, 1, 0};
-  const float mx = r0.x, my = r0.y, a = r0.z, b = r0.w, c = r1.x, rho = r1.y;
-  if (!(rho > 0.0f)) return bx;
-  const float det = a * c - b * b;
-  if (!(det > 0.0f) || !(a > 0.0f) || !(c > 0.0f)) return bx;
-  const float rb = rho * (1.0f + 0x1p-9f);
-  const float ex = sqrtf(rb * c / det), ey = sqrtf(rb * a / det);
-  const float xl = mx - ex - 2.0f, xh = mx + ex + 2.0f;
-  const float yl = my - ey - 2.0f, yh = my + ey + 2.0f;
-  if (!(xh >= 0.0f) || !(yh >= 0.0f) || !(xl <= float(V.W)) || !(yl <= float(V.H))) return bx;
-  bx.tx0 = int(floorf(fmaxf(xl, 0.0f) / float(V.tile_w)));
-  bx.tx1 = min(V.tiles_x - 1, int(floorf(fminf(xh, float(V.W)) / float(V.tile_w))));
-  bx.ty0 = int(floorf(fmaxf(yl, 0.0f) / float(V.tile_h)));
-  bx.ty1 = min(V.tiles_y - 1, int(floorf(fminf(yh, float(V.H)) / float(V.tile_h))));
-  return bx;
+  return tile_box_of(r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, V.W, V.H, V.tile_w, V.tile_h);
 }
 
 __device__ __forceinline__ bool record_hits_tile(const float4 r0, const float4 r1, const DevView& V,

@@ -7,5 +7,5 @@ method's arithmetic: no conditioning, projection, binning or compositing.
 """
 from .scenes import (  # noqa: F401
     SceneSpec, ViewSpec, param_count, make_scene, make_view, look_at_view,
-    make_target, make_config, CONFIG_NAMES, make_splat_records,
+    make_target, make_config, CONFIG_NAMES, make_splat_records, make_elongated_records,
 )

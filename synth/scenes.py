@@ -298,3 +298,33 @@ def make_splat_records(n: int, width: int, height: int, seed: int,
     culled = rng.uniform(size=n) < cull_frac
     rec[culled, 5] = 0.0
     return rec.astype(np.float32)
+
+
+def make_elongated_records(n: int, width: int, height: int, seed: int,
+                           *, ratio=(1e4, 1e8), minor=(0.3, 4.0)) -> np.ndarray:
+    """Screen-space records of very elongated splats, float32 [n][12] (the
+    layout of ``make_splat_records``): the 2-D covariance has eigenvalues
+    lam1 in ``minor`` (px^2) and lam1 * ratio, ratio log-uniform in
+    ``ratio``, at a uniform angle (a fifth of them within 1e-3 rad of an
+    axis); the conic is its inverse, rounded to float32 (for the largest
+    ratios the rounded conic can lose positive definiteness)."""
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(0.0, math.pi, size=n)
+    near_axis = rng.uniform(size=n) < 0.2
+    th[near_axis] = (rng.integers(0, 4, size=int(near_axis.sum())) * (math.pi / 2)
+                     + rng.uniform(-1e-3, 1e-3, size=int(near_axis.sum())))
+    l1 = rng.uniform(minor[0], minor[1], size=n)
+    l2 = l1 * np.exp(rng.uniform(math.log(ratio[0]), math.log(ratio[1]), size=n))
+    cs, sn = np.cos(th), np.sin(th)
+    rec = np.zeros((n, 12), dtype=np.float64)
+    rec[:, 0] = rng.uniform(-0.2 * width, 1.2 * width, size=n)
+    rec[:, 1] = rng.uniform(-0.2 * height, 1.2 * height, size=n)
+    rec[:, 2] = cs * cs / l1 + sn * sn / l2
+    rec[:, 3] = cs * sn * (1.0 / l1 - 1.0 / l2)
+    rec[:, 4] = sn * sn / l1 + cs * cs / l2
+    rec[:, 5] = rng.uniform(0.05, 0.999, size=n)
+    rec[:, 6] = rng.uniform(0.05, 1.0, size=n)
+    rec[:, 7] = np.exp(rng.uniform(math.log(0.3), math.log(30.0), size=n))
+    rec[:, 8:11] = rng.uniform(0.0, 1.0, size=(n, 3))
+    rec[:, 11] = rng.uniform(0.3, 10.0, size=n)
+    return rec.astype(np.float32)

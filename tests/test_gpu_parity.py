@@ -15,7 +15,7 @@ from _gpu_common import (GRAD_BLOCKS, bin_reference, compare_images, gpu_ready, 
                          grad_violations, log, oracle_view, to_dev)
 from oracle import preprocess as opp
 from oracle import raster as oraster
-from synth import look_at_view, make_config, make_splat_records, make_view
+from synth import look_at_view, make_config, make_elongated_records, make_splat_records, make_view
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_ready(), reason="needs a GPU")]
@@ -101,6 +101,27 @@ def test_bin_sort_bit_exact_multi_view():
                            for k, (n, v) in enumerate(zip(ns, cfg["views"]))])
     r, frame, K, keys, vals, ranges = _inject_and_sort(cfg, recs)
     sk, sv, rg = bin_reference(recs, [_V(v, n) for v, n in zip(cfg["views"], ns)])
+    assert K == sk.size
+    np.testing.assert_array_equal(keys, sk)
+    np.testing.assert_array_equal(vals, sv)
+    np.testing.assert_array_equal(ranges, rg)
+
+
+@pytest.mark.parametrize("ratio", [(1e3, 1e5), (1e5, 1e7), (1e7, 1e8)])
+def test_bin_sort_bit_exact_on_elongated_splats(ratio):
+    """Splats with covariance axis ratios up to 1e8 (at the top some float32
+    conics are no longer positive definite: every tile is a candidate): the
+    candidate boxes, taken in float64, hold every tile the exact test
+    accepts, so keys, values and ranges are bit-exact."""
+    log(f"[bin_sort] elongated {ratio}")
+    W, H, n = 320, 200, 3000
+    cfg = make_config("cfg0", n=n, width=W, height=H)
+    recs = make_elongated_records(n, W, H, seed=int(math.log10(ratio[0])), ratio=ratio)
+    a, b, c = (recs[:, k].astype(np.float64) for k in (2, 3, 4))
+    log(f"  float32 conics not positive definite: {int((a * c - b * b <= 0).sum())}")
+    r, frame, K, keys, vals, ranges = _inject_and_sort(cfg, recs)
+    sk, sv, rg = bin_reference(recs, [_V(cfg["views"][0], n)])
+    log(f"  pairs {K}, longest tile {int((rg[:, 1] - rg[:, 0]).max())}")
     assert K == sk.size
     np.testing.assert_array_equal(keys, sk)
     np.testing.assert_array_equal(vals, sv)
@@ -205,7 +226,7 @@ def test_render_forward_matches_oracle(case):
     assert nbad == 0 and err <= 1e-4
     terr, _, tbad = compare_images(g["t_final"][0], o["t_final"], o["flags"], 1e-4)
     assert tbad == 0
-    assert nflag <= 0.01 * o["flags"].size
+    assert nflag <= 0.001 * o["flags"].size     # observed: at most 2 of 32,400
 
 
 def test_raster_only_parity_on_identical_records():

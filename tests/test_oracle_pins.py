@@ -632,6 +632,31 @@ def test_binning_is_exact_and_complete_brute_force():
     assert n_hits > 20
 
 
+@pytest.mark.parametrize("kind", ["ordinary", "elongated", "far"])
+def test_binning_window_changes_nothing(kind):
+    """The binning reference tests each record's tiles inside a float64
+    window of its ellipse; scanning every tile of the view gives the same
+    keys and values, for ordinary records, very elongated ones (axis ratios
+    up to 1e8, some float32 conics indefinite) and records far off screen."""
+    from synth import make_elongated_records
+    W, H = 200, 120
+    if kind == "ordinary":
+        rec = make_splat_records(3000, W, H, seed=4, max_extent=50.0)
+    elif kind == "elongated":
+        rec = make_elongated_records(3000, W, H, seed=5, ratio=(1e3, 1e8))
+    else:
+        rec = make_splat_records(500, W, H, seed=6, max_extent=40.0)
+        rec[:, 0] += np.float32(3 * W)
+        rec[::2, 0] -= np.float32(6 * W)
+        rec[::3, 1] += np.float32(1e7)
+    k1, v1 = raster.bin_view(rec, W, H, 16, 16)
+    k2, v2 = raster.bin_view(rec, W, H, 16, 16, full_scan=True)
+    np.testing.assert_array_equal(k1, k2)
+    np.testing.assert_array_equal(v1, v2)
+    if kind != "far":
+        assert k1.size > 1000
+
+
 @pytest.mark.parametrize("a,b,c", [(1.0, 0.0, 1.0), (2.0, 0.5, 1.0), (0.5, -0.2, 3.0)])
 def test_tile_test_threshold_golden(a, b, c):
     """The overlap rule (tile pixel-centre rectangle, min r <= rho (1 + 2^-10))
