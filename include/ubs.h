@@ -12,8 +12,8 @@
  *   ubs_preprocess  condition each primitive on the view's query, project
  *                   it to a screen-space splat record (Section 4.2-4.3,
  *                   Section 3 projection);
- *   ubs_bin_sort    emit one (tile, depth) key per overlapped tile, radix
- *                   sort the keys, find each tile's range;
+ *   ubs_bin_sort    emit one (tile, depth) key per overlapped tile, sort
+ *                   each tile's keys, find each tile's range;
  *   ubs_render_fwd  alpha-composite each tile front to back (Section 3
  *                   compositing with the Beta kernel of Section 4.3);
  *   ubs_render_bwd  adjoint of the two previous steps: gradient of the loss
@@ -47,7 +47,7 @@ extern "C" {
 #endif
 
 #define UBS_ABI_VERSION 1
-#define UBS_MAX_QUERY_DIMS 4  /* C <= 4: N <= 7 */
+#define UBS_MAX_QUERY_DIMS 7  /* C <= 7: N <= 10 (C = 1, 2 unsupported) */
 #define UBS_MAX_VIEWS 4096
 #define UBS_MAX_SCENES 256
 
@@ -258,6 +258,10 @@ ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
 
 /*
  * ubs_bin_sort -- tile binning and (tile, depth) sort.
+ * Paper: the "standard splatting" rasterisation the renderer builds on
+ * (Section 4.5: splats binned to screen tiles and depth-ordered per tile),
+ * with a splat's extent given by its Mahalanobis distance r (Section 3,
+ * equation r) and its support r <= rho (Beta kernel, Section 3 / 4.3).
  * Reads the records in ws (written by ubs_preprocess, or by the caller in
  * the documented record format after a ubs_preprocess call on the same
  * frame).  A record overlaps a tile iff the minimum of r over the rectangle
@@ -289,6 +293,11 @@ ubs_status ubs_render_fwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
 
 /*
  * ubs_render_bwd -- adjoint of ubs_render_fwd and ubs_preprocess.
+ * Paper: the gradient of the Section 3 compositing C = sum_i c_i alpha_i
+ * prod_{j<i} (1 - alpha_j) with respect to every record, chained through
+ * the projection (Section 3), the Beta-modulated conditioning and opacity
+ * (Section 4.3) and the spatial-orthogonal Cholesky covariance (Section 4.2)
+ * to every primitive parameter.
  * Walks each tile back to front, recovering the transmittance by division
  * instead of storing it, reduces per-record gradients across the tile and
  * accumulates them with atomics, then chains them through the projection,
