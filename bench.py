@@ -34,23 +34,30 @@ HBM_PEAK_GBS = 8000.0
 # (non-packed fp32; the kernels are built without packed fp32 instructions).
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
-# Algorithmic VALU lane-operations of the backward raster per unit of work,
-# counted from the arithmetic itself (an FMA, add, mul, min or compare = 1;
-# exp2, log2 and reciprocal = 4, they issue at quarter rate).  Only work the
-# adjoint needs is counted: the cross-lane sums, the LDS staging and the
+# Algorithmic VALU lane-operations of the rasters per unit of work, counted
+# from the arithmetic itself (an FMA, add, mul, min or compare = 1; exp2,
+# log2 and reciprocal = 4, they issue at quarter rate).  Only work the
+# method needs is counted: the cross-lane sums, the LDS staging and the
 # lanes idle under divergence are overheads of the implementation.
+# Backward raster:
 #   eval     (pixel, record) visited before the pixel's last contributor:
 #            dy, r = A + dy (B + c dy), support test                      4
 #   support  r <= rho: 1 - r, log2, fma with beta and log2 o, exp2,
 #            min 0.99, alpha test                                         12
 #   contrib  alpha >= 1/255: 1 - alpha, rcp, T/(1-alpha), weight, three
-#            colour-gradient sums, d alpha (11), running colour (6)       27
-#   grad     sigma < 0.99 as well: opacity and beta terms, d sigma / d r
-#            (rcp of 1 - r) and the three moment sums                     15
+#            colour-gradient sums (6), c - S shared by d alpha and the
+#            running colour S += alpha (c - S) (3 + 3)                    20
+#   grad     sigma < 0.99 as well: d alpha = T/(1-alpha) g.(c - S) (4),
+#            s = sigma d alpha, opacity and beta sums, rcp of 1 - r and
+#            s/(1 - r), the three moment sums                             13
 #   pair     per (tile, record): dx and the column terms of the tile's 16
 #            pixel columns (4 each), 1/o, the ten sums turned into the
 #            record-field gradients (14)                                  64 + 4 + 14
 BWD_OPS = {"eval": 4, "support": 12, "contrib": 20, "grad": 13, "pair": 82}
+# Forward raster: eval and support as above; contrib: T (1 - alpha) and its
+# stop test, weight alpha T, three colour FMAs, the contributor count (8);
+# pair: the column terms (64) and log2 o (4).
+FWD_OPS = {"eval": 4, "support": 12, "contrib": 8, "pair": 68}
 
 WORKLOADS = {
     "headline": ("headline", "1,000,000 7-D Beta primitives (quaternion rotation), one "
@@ -171,44 +178,93 @@ def raster_bwd_work(r, view, n_pairs: int, tile: int = 16, chunk: int = 8192) ->
     return tot
 
 
-def cpu_baseline(cfg, rows: int = 24, sub: int = 100_000) -> dict:
-    """The oracle timed on a bounded sample of the same frame (one thread)."""
+def _oracle_band(job):
+    """One row band of the oracle's compositing, forward and adjoint, in a
+    worker process of its own (the oracle's C code is single-threaded);
+    returns the seconds it took."""
+    path, W, H, y0, y1 = job
+    import numpy as np
+    from oracle import raster as oraster
+    rec = np.load(path)
+    dimg = np.zeros((H, W, 3))
+    dimg[y0:y1] = np.random.default_rng(y0).normal(size=(y1 - y0, W, 3)) * 1e-6
+    t0 = time.perf_counter()
+    oraster.render_fwd(rec, W, H, rows=(y0, y1))
+    oraster.render_bwd(rec, W, H, dimg, rows=(y0, y1))
+    return time.perf_counter() - t0
+
+
+def host_cpu() -> dict:
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "usable": usable}
+
+
+def cpu_baseline(cfg, rows: int = 32, sub: int = 100_000, max_workers: int = 16) -> dict:
+    """The oracle timed on a bounded sample of the same frame, on one host
+    thread and on all the host threads this process may use (at most
+    max_workers): the per-primitive steps (torch float64, forward and
+    backward) on `sub` primitives, and the compositing (C, forward and
+    adjoint) on `rows` rows in one band per worker, spread evenly over the
+    image; both scaled linearly to the whole frame."""
+    import multiprocessing as mp
+    import tempfile
+
     import numpy as np
     import torch
     from oracle import preprocess as opp
-    from oracle import raster as oraster
 
-    torch.set_num_threads(1)
+    cpu = host_cpu()
+    workers = max(1, min(max_workers, cpu["usable"] or 1))
     sc, view = cfg["scenes"][0], cfg["views"][0]
     n = sc.n
     sub = min(sub, n)
-    # per-primitive steps forward + backward on a subset of the primitives
-    Ps = torch.tensor(sc.params[:, :sub].astype(np.float64), requires_grad=True)
-    t0 = time.perf_counter()
-    out = opp.preprocess(Ps, sc.dim, sc.rot, view)
-    out["rec"].backward(torch.ones_like(out["rec"]))
-    t_pre = (time.perf_counter() - t0) * (n / sub)
+    t_pre = {}
+    for threads in (1, workers):
+        torch.set_num_threads(threads)
+        Ps = torch.tensor(sc.params[:, :sub].astype(np.float64), requires_grad=True)
+        t0 = time.perf_counter()
+        out = opp.preprocess(Ps, sc.dim, sc.rot, view)
+        out["rec"].backward(torch.ones_like(out["rec"]))
+        t_pre[threads] = (time.perf_counter() - t0) * (n / sub)
     # records of every primitive (setup for the compositing sample, untimed)
     recs = []
     with torch.no_grad():
         for k in range(0, n, 200_000):
             P = torch.tensor(sc.params[:, k:k + 200_000].astype(np.float64))
             recs.append(opp.preprocess(P, sc.dim, sc.rot, view)["rec"].numpy())
-    rec = np.concatenate(recs)
     H, W = view.height, view.width
-    y0 = max(0, H // 2 - rows // 2)
-    band = (y0, min(H, y0 + rows))
-    rng = np.random.default_rng(0)
-    dimg = rng.normal(size=(H, W, 3)) * 1e-6
-    t0 = time.perf_counter()
-    oraster.render_fwd(rec, W, H, rows=band)
-    oraster.render_bwd(rec, W, H, dimg, rows=band)
-    t_band = (time.perf_counter() - t0) * (H / (band[1] - band[0]))
-    total = t_pre + t_band
-    return {"value": 1.0 / total, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": (f"per-primitive steps fwd+bwd on {sub:,} of {n:,} primitives scaled x{n / sub:g}; "
-                       f"compositing fwd+bwd on rows {band[0]}-{band[1]} of {H} scaled "
-                       f"x{H / (band[1] - band[0]):g}; float64, 1 thread")}
+    per = max(1, rows // workers)
+    starts = [int(round((k + 0.5) * H / workers - per / 2)) for k in range(workers)]
+    jobs_rows = [(max(0, y), min(H, max(0, y) + per)) for y in starts]
+    sampled = sum(y1 - y0 for y0, y1 in jobs_rows)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "records.npy")
+        np.save(path, np.concatenate(recs))
+        jobs = [(path, W, H, y0, y1) for y0, y1 in jobs_rows]
+        with mp.get_context("spawn").Pool(workers) as pool:
+            pool.map(_oracle_band, jobs[:1])          # start-up of the workers, untimed
+            t0 = time.perf_counter()
+            band_s = pool.map(_oracle_band, jobs)
+            wall = time.perf_counter() - t0
+    scale = H / sampled
+    one = t_pre[1] + sum(band_s) * scale
+    many = t_pre[workers] + wall * scale
+    return {"value": 1.0 / many, "unit": "frames/s", "cores": workers, "kind": "oracle",
+            "single_thread_value": 1.0 / one, "cpu_model": cpu["model"], "nproc": cpu["nproc"],
+            "usable_cpus": cpu["usable"],
+            "sample": (f"per-primitive steps fwd+bwd (torch float64) on {sub:,} of {n:,} primitives "
+                       f"scaled x{n / sub:g}; compositing fwd+bwd (C float64, one process per band) "
+                       f"on {len(jobs_rows)} bands of {per} rows spread over {H} scaled "
+                       f"x{scale:.1f}; value: {workers} threads/processes, single_thread_value: "
+                       f"the same sample on one thread")}
 
 
 def timed_steps(gf, steps: int, eager: bool):
@@ -302,15 +358,34 @@ def run_single(args, name, desc):
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
             "traffic": recorded_traffic(name, dom)}
-    if dom == "raster_bwd" and view.width * view.height > 0:
+    work = raster_bwd_work(r, view, c["K"]) if view.width * view.height > 0 else None
+    if dom == "raster_bwd" and work is not None:
         # the backward raster is bound by vector ALU work, not by bytes
-        work = raster_bwd_work(r, view, c["K"])
         tops = work["lane_ops"] / (stages_ms[dom] * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": round(tops, 3), "peak": VALU_PEAK_TOPS,
                 "unit": "T lane-ops/s", "frac": round(tops / VALU_PEAK_TOPS, 4),
                 "traffic": recorded_traffic(name, dom), "work": work,
                 "hbm": {"achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(ach / HBM_PEAK_GBS, 5)}}
+    # the frame against both rooflines: B = compulsory HBM bytes of the
+    # frame (8 F P for params in and dparams out, Pv (176 + 4 F) for the
+    # records, 2-D gradients and the visible parameters read again, 172 K
+    # for keys, values, record gathers and atomics, 76 A for the pixels,
+    # 16 G for the tile ranges); ALU = the rasters' algorithmic lane-ops
+    # (the per-primitive float64 work is left out, so T_bound is a lower
+    # bound of the frame time)
+    F, P, Pv, K, A, G = c["F"], c["P"], c["Pv"], c["K"], c["A"], c["G"]
+    B = (8.0 * F * P if backward else 4.0 * F * P) + Pv * (176.0 + 4.0 * F) + 172.0 * K + 76.0 * A + 16.0 * G
+    alu = 0.0
+    if work is not None:
+        alu = sum(FWD_OPS[k] * work[k] for k in FWD_OPS)
+        if backward:
+            alu += work["lane_ops"]
+    t_s = ms * 1e-3
+    t_hbm, t_alu = B / (HBM_PEAK_GBS * 1e9), alu / (VALU_PEAK_TOPS * 1e12)
+    frame = {"bytes": B, "hbm_frac": round(t_hbm / t_s, 4), "alu_lane_ops": alu,
+             "alu_frac": round(t_alu / t_s, 4), "t_bound_ms": round(max(t_hbm, t_alu) * 1e3, 4),
+             "t_bound_frac": round(max(t_hbm, t_alu) / t_s, 4)}
     res = {
         "metric": METRIC if name == "headline" else f"{'fwd+bwd' if backward else 'fwd'} frames/s ({name})",
         "value": round(1000.0 / ms, 3), "unit": "frames/s", "n_gpus": 1,
@@ -323,6 +398,7 @@ def run_single(args, name, desc):
         "roofline": roof,
         "kernel_sources": kernel_sources_digest(),
         "frame_hbm_frac": round(frame_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+        "frame": frame,
         "stages_ms": {k: round(v, 4) for k, v in stages_ms.items()},
         "eager_ms_per_step": round(eager_ms, 4),
         "per_primitive_math": "f32" if args.pre_fp32 else "f64",
@@ -331,7 +407,8 @@ def run_single(args, name, desc):
     if not args.no_cpu_baseline and name == "headline":
         log("[bench] timing the oracle on a bounded CPU sample")
         res["cpu_baseline"] = cpu_baseline(cfg)
-        res["cpu_baseline"]["value"] = round(res["cpu_baseline"]["value"], 6)
+        for k in ("value", "single_thread_value"):
+            res["cpu_baseline"][k] = round(res["cpu_baseline"][k], 6)
     return res
 
 

@@ -136,22 +136,22 @@ __device__ __forceinline__ void raster_fwd_tile(
         const float dy = float(py0 + k * RSTEP) + 0.5f - g0.y;
         const float r = eval_r(ct, g1.x, dy);
         if (!(r <= g1.y)) continue;
+        // one branch per pixel: skipping (alpha below 1/255) and stopping
+        // are taken by selects
         float l2;
         const float sigma = eval_sigma(r, g1.z, g1.w, &l2);
         const float alpha = fminf(kAlphaMax, sigma);
-        if (alpha < kAlphaMin) continue;
         const float test = T[k] * (1.0f - alpha);
-        if (test < kTStop) {
-          done |= 1u << k;
-          T[k] = -fabsf(T[k]);
-          continue;
-        }
-        const float w = alpha * T[k];
+        const bool hit = alpha >= kAlphaMin;
+        const bool con = hit && test >= kTStop;
+        const bool stop = hit && !(test >= kTStop);
+        done |= stop ? (1u << k) : 0u;
+        const float w = con ? alpha * T[k] : 0.0f;
         cr[k] += g2.x * w;
         cg[k] += g2.y * w;
         cb[k] += g2.z * w;
-        T[k] = test;
-        last[k] = b0 - start + uint32_t(j) + 1u;
+        T[k] = con ? test : (stop ? -fabsf(T[k]) : T[k]);
+        last[k] = con ? b0 - start + uint32_t(j) + 1u : last[k];
       }
       if (done == kAll) break;
     }
@@ -329,17 +329,20 @@ __device__ __forceinline__ void raster_bwd_tile(
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
-        if (pos >= last[k]) continue;
         const float dy = float(py0 + k * RSTEP) + 0.5f - g0.y;
         const float r = eval_r(ct, g1.x, dy);
-        if (!(r <= g1.y)) continue;
+        // one branch per pixel: the rare cases inside it (alpha below
+        // 1/255 at the support's rim, sigma at the 0.99 clamp) are taken
+        // by zeroing alpha or sigma, which makes their updates no-ops
+        if (!(pos < last[k] && r <= g1.y)) continue;
         float l2;
-        const float sigma = eval_sigma(r, g1.z, g1.w, &l2);
-        const float alpha = fminf(kAlphaMax, sigma);
-        if (alpha < kAlphaMin) continue;
-        any = true;
+        const float sigma0 = eval_sigma(r, g1.z, g1.w, &l2);
+        const bool con = fminf(kAlphaMax, sigma0) >= kAlphaMin;
+        any = any || con;
+        const float alpha = con ? fminf(kAlphaMax, sigma0) : 0.0f;
+        const float sigma = (con && sigma0 < kAlphaMax) ? sigma0 : 0.0f;
         const float ioma = fast_rcp(1.0f - alpha);
-        const float Ti = T[k] * ioma;
+        const float Ti = con ? T[k] * ioma : T[k];
         const float w = alpha * Ti;
         a_r += gR[k] * w;
         a_g += gG[k] * w;
@@ -347,18 +350,16 @@ __device__ __forceinline__ void raster_bwd_tile(
         // colour in front of the record minus the colour behind it; the
         // colour behind updates as S += alpha (c - S)
         const float er = g2.x - Sr[k], eg = g2.y - Sg[k], eb = g2.z - Sb[k];
-        if (sigma < kAlphaMax) {
-          const float dot = gR[k] * er + gG[k] * eg + gB[k] * eb;
-          const float dalpha = HAS_DT ? Ti * dot - gTf[k] * ioma : Ti * dot;
-          const float sd = sigma * dalpha;
-          a_o += sd;
-          a_be += sd * l2;
-          const float q = sd * fast_rcp(1.0f - r);
-          a_dr += q;
-          const float qy = q * dy;
-          a_dry += qy;
-          a_dryy += qy * dy;
-        }
+        const float dot = gR[k] * er + gG[k] * eg + gB[k] * eb;
+        const float dalpha = HAS_DT ? Ti * dot - gTf[k] * ioma : Ti * dot;
+        const float sd = sigma * dalpha;
+        a_o += sd;
+        a_be += sd * l2;
+        const float q = sd * fast_rcp(1.0f - r);
+        a_dr += q;
+        const float qy = q * dy;
+        a_dry += qy;
+        a_dryy += qy * dy;
         Sr[k] += alpha * er;
         Sg[k] += alpha * eg;
         Sb[k] += alpha * eb;

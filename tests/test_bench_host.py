@@ -55,3 +55,12 @@ def test_gpus_other_than_one_exit_with_message(capsys, monkeypatch):
     monkeypatch.setattr("sys.argv", ["bench.py", "--gpus", "2"])
     assert bench.main() == 2
     assert "one GPU" in capsys.readouterr().err
+
+
+def test_cpu_baseline_reports_one_and_all_threads():
+    cfg = make_config("cfg0", n=500, width=64, height=48)
+    cb = bench.cpu_baseline(cfg, rows=8, sub=200, max_workers=2)
+    assert cb["kind"] == "oracle" and cb["unit"] == "frames/s"
+    assert cb["cores"] == min(2, cb["usable_cpus"])
+    assert cb["value"] > 0 and cb["single_thread_value"] > 0
+    assert cb["nproc"] >= 1 and isinstance(cb["cpu_model"], str)
