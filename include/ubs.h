@@ -210,7 +210,9 @@ typedef struct {
  *             (0, 0) for an empty tile.
  *   ncontrib  uint32 [n_pixels] per pixel: one past the position (within
  *             its tile's range) of its last contributor.
- *   grad2d    float32 [n_records][10] d loss / d record fields 0-4, 6-10.
+ *   grad2d    float32 [n_records][10] d loss / d record fields 0-4, 6-10,
+ *             after ubs_render_bwd (rows of culled records, rho <= 0, are
+ *             not written).
  * Other regions are private scratch.
  */
 typedef struct {
@@ -236,7 +238,7 @@ typedef struct {
   uint32_t spill;            /* 1 if some tile met more records than
                                 tuning.tile_slots: the frame took the second,
                                 emitting binning pass */
-  uint32_t _pad[6];
+  uint32_t _pad[6];          /* internal */
 } ubs_status_block;
 
 /*

@@ -21,7 +21,7 @@ hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const 
 hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
                             uint32_t n_records, uint32_t* tile_counts, uint32_t* hit_mask,
                             uint32_t* big_list, uint32_t* big_count, unsigned long long* slots,
-                            uint32_t slot_cap, DevStatus* status, hipStream_t st);
+                            uint32_t slot_cap, DevStatus* status, float* grad2d, hipStream_t st);
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
                        DevStatus* status, unsigned long long capacity, hipStream_t st,
                        unsigned long long* total_out);
@@ -42,7 +42,8 @@ hipError_t launch_raster_fwd(int tw, int th, int batch, uint32_t persistent_bloc
                              uint32_t n_tiles, float* image, float* t_ws, float* t_user,
                              uint32_t* ncontrib, hipStream_t st);
 hipError_t launch_raster_bwd(int tw, int th, int batch, uint32_t persistent_blocks,
-                             uint32_t* work, const float* records, const uint32_t* values,
+                             uint32_t* work, uint32_t* grad_dirty, const float* records,
+                             const uint32_t* values,
                              const uint32_t* ranges, const DevView* views, int n_views,
                              uint32_t n_tiles, const float* t_ws, const uint32_t* ncontrib,
                              const float* d_image, const float* d_tfinal, const float* l1_image,
@@ -84,6 +85,23 @@ __global__ void fill_f32_kernel(float* __restrict__ p, size_t n) {
 
 // Same with 16-byte stores: p 16-byte aligned; the n % 4 tail by thread 0.
 __global__ void fill_f32x4_kernel(float* __restrict__ p, size_t n) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  float4* q = reinterpret_cast<float4*>(p);
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (size_t k = i; k < n / 4; k += stride) store_stream(&q[k], z);
+  if (i == 0)
+    for (size_t k = n & ~size_t(3); k < n; ++k) store_stream(&p[k], 0.0f);
+}
+
+// The record gradients before a backward raster: the binning zeroed the
+// rows of the live records, and the backward raster marks them dirty; only
+// if a backward pass has run since the binning (a second ubs_render_bwd of
+// the same frame) is every row cleared again.  A small fixed grid, so that
+// the usual case costs one short launch.
+__global__ void __launch_bounds__(256) grad_prepare_kernel(float* __restrict__ p, size_t n,
+                                                           const DevStatus* __restrict__ status) {
+  if (!status->grad_dirty) return;
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   float4* q = reinterpret_cast<float4*>(p);
@@ -395,7 +413,8 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
   uint32_t* hit_mask = at<uint32_t>(ws, L.off_hit_mask);
   auto* slots = at<unsigned long long>(ws, L.off_slots);
   UBS_HIP(launch_bin_count(records, views, frame->n_views, n_rec, tile_counts, hit_mask, big_list,
-                           big_count, slots, L.tile_slots, status, s));
+                           big_count, slots, L.tile_slots, status, at<float>(ws, L.pub.off_grad2d),
+                           s));
   stage_mark(frame, UBS_STAGE_BIN_COUNT, 1, s);
   stage_mark(frame, UBS_STAGE_SCAN, 0, s);
   // segment starts of the tiles; the total sets pairs_needed and overflow
@@ -451,15 +470,17 @@ ubs_status ubs_render_bwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
   const Layout& L = p.L;
   float* grad2d = at<float>(ws, L.pub.off_grad2d);
   const size_t ng = size_t(L.pub.n_records) * kGradFloats;
+  DevStatus* status = at<DevStatus>(ws, L.pub.off_status);
   stage_mark(frame, UBS_STAGE_GRAD_CLEAR, 0, s);
-  launch_fill_zero(grad2d, ng, s);
+  if (ng > 0)
+    hipLaunchKernelGGL(grad_prepare_kernel, dim3(512), dim3(256), 0, s, grad2d, ng, status);
   stage_mark(frame, UBS_STAGE_GRAD_CLEAR, 1, s);
   const float l1_scale = L.pub.n_pixels > 0 ? float(1.0 / (3.0 * double(L.pub.n_pixels))) : 0.0f;
   const DevView* views = at<DevView>(ws, L.off_views);
   stage_mark(frame, UBS_STAGE_RASTER_BWD, 0, s);
-  DevStatus* status = at<DevStatus>(ws, L.pub.off_status);
   UBS_HIP(launch_raster_bwd(L.tile_w, L.tile_h, frame->tuning.batch_depth, persistent_blocks(frame),
-                            &status->work_counter[1], at<float>(ws, L.pub.off_records),
+                            &status->work_counter[1], &status->grad_dirty,
+                            at<float>(ws, L.pub.off_records),
                             at<uint32_t>(ws, L.pub.off_values), at<uint32_t>(ws, L.pub.off_ranges),
                             views, frame->n_views, uint32_t(L.pub.n_tiles),
                             at<float>(ws, L.off_tfinal_ws), at<uint32_t>(ws, L.pub.off_ncontrib),

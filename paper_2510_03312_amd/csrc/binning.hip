@@ -220,7 +220,8 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict_
                                                         uint32_t* __restrict__ big_count,
                                                         unsigned long long* __restrict__ slots,
                                                         uint32_t slot_cap,
-                                                        DevStatus* __restrict__ status) {
+                                                        DevStatus* __restrict__ status,
+                                                        float* __restrict__ grad2d) {
   __shared__ uint32_t s_list[kBinWaves][kBinRecPerWave];
   __shared__ uint32_t s_excl[kBinWaves][65];
   __shared__ unsigned long long s_key[kBinWaves][64];
@@ -239,6 +240,14 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict_
   for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
     const bool active = c0 + lane < cnt;
     const uint32_t rec = active ? list[c0 + lane] : 0u;
+    // the backward raster accumulates into the gradient rows of exactly
+    // these records: they start at zero (the rows of culled records are
+    // never read)
+    if (active) {
+      float2* gp = reinterpret_cast<float2*>(grad2d + size_t(rec) * kGradFloats);
+#pragma unroll
+      for (int q = 0; q < kGradFloats / 2; ++q) gp[q] = make_float2(0.0f, 0.0f);
+    }
     const BinRec b = load_bin_rec(records, views, n_views, rec, active);
     const bool small = b.n_cand > 0 && b.n_cand <= kSmallBox;
     const uint32_t nc = small ? uint32_t(b.n_cand) : 0u;
@@ -514,11 +523,11 @@ constexpr unsigned kBigBlocks = 1024;
 hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
                             uint32_t n_records, uint32_t* tile_counts, uint32_t* hit_mask,
                             uint32_t* big_list, uint32_t* big_count, unsigned long long* slots,
-                            uint32_t slot_cap, DevStatus* status, hipStream_t st) {
+                            uint32_t slot_cap, DevStatus* status, float* grad2d, hipStream_t st) {
   if (n_records == 0) return hipSuccess;
   hipLaunchKernelGGL(bin_count_kernel, dim3(bin_blocks(n_records)), dim3(256), 0, st, records,
                      views, n_views, n_records, tile_counts, hit_mask, big_list, big_count, slots,
-                     slot_cap, status);
+                     slot_cap, status, grad2d);
   return hipGetLastError();
 }
 
@@ -703,6 +712,7 @@ __global__ void __launch_bounds__(256) bin_prepare_kernel(uint32_t* __restrict__
   __syncthreads();
   if (threadIdx.x == 0) {
     status->spill = 0u;
+    status->grad_dirty = 0u;
     status->n_visible = s_sum[0][0] + s_sum[0][1] + s_sum[0][2] + s_sum[0][3];
     status->n_nonfinite = s_sum[1][0] + s_sum[1][1] + s_sum[1][2] + s_sum[1][3];
   }

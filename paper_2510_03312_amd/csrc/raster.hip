@@ -416,15 +416,19 @@ __device__ __forceinline__ void raster_bwd_tile(
   }
 }
 
+// grad_dirty: set, so that a later backward pass over the same binning
+// clears the record gradients first.
 template <int TW, int TH, int BATCH>
 __global__ void __launch_bounds__(64) raster_bwd_kernel(
     const float* __restrict__ records, const uint32_t* __restrict__ values,
     const uint32_t* __restrict__ ranges, const DevView* __restrict__ views, int n_views,
-    uint32_t n_tiles, uint32_t* __restrict__ work, const float* __restrict__ t_ws,
+    uint32_t n_tiles, uint32_t* __restrict__ work, uint32_t* __restrict__ grad_dirty,
+    const float* __restrict__ t_ws,
     const uint32_t* __restrict__ ncontrib, const float* __restrict__ d_image,
     const float* __restrict__ d_tfinal, const float* __restrict__ l1_image,
     const float* __restrict__ l1_target, float l1_scale, float* __restrict__ grad2d) {
   __shared__ float4 s0[BATCH], s1[BATCH], s2[BATCH];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *grad_dirty = 1u;
   for (uint32_t tile = next_tile(work, true); tile < n_tiles; tile = next_tile(work, false)) {
     if (d_tfinal)
       raster_bwd_tile<TW, TH, BATCH, true>(tile, s0, s1, s2, records, values, ranges, views,
@@ -472,15 +476,16 @@ static hipError_t raster_fwd_t(const RasterLaunch& g, const float* records, cons
 }
 
 template <int TW, int TH, int BATCH>
-static hipError_t raster_bwd_t(const RasterLaunch& g, const float* records, const uint32_t* values,
-                               const uint32_t* ranges, const DevView* views, int n_views,
+static hipError_t raster_bwd_t(const RasterLaunch& g, uint32_t* grad_dirty, const float* records,
+                               const uint32_t* values, const uint32_t* ranges,
+                               const DevView* views, int n_views,
                                const float* t_ws, const uint32_t* ncontrib, const float* d_image,
                                const float* d_tfinal, const float* l1_image,
                                const float* l1_target, float l1_scale, float* grad2d,
                                hipStream_t st) {
   hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, BATCH>), dim3(g.grid), dim3(64), 0, st, records,
-                     values, ranges, views, n_views, g.n_tiles, g.work, t_ws, ncontrib, d_image,
-                     d_tfinal, l1_image, l1_target, l1_scale, grad2d);
+                     values, ranges, views, n_views, g.n_tiles, g.work, grad_dirty, t_ws, ncontrib,
+                     d_image, d_tfinal, l1_image, l1_target, l1_scale, grad2d);
   return hipGetLastError();
 }
 
@@ -522,7 +527,8 @@ hipError_t launch_raster_fwd(int tw, int th, int batch, uint32_t persistent_bloc
 }
 
 hipError_t launch_raster_bwd(int tw, int th, int batch, uint32_t persistent_blocks,
-                             uint32_t* work, const float* records, const uint32_t* values,
+                             uint32_t* work, uint32_t* grad_dirty, const float* records,
+                             const uint32_t* values,
                              const uint32_t* ranges, const DevView* views, int n_views,
                              uint32_t n_tiles, const float* t_ws, const uint32_t* ncontrib,
                              const float* d_image, const float* d_tfinal, const float* l1_image,
@@ -530,8 +536,8 @@ hipError_t launch_raster_bwd(int tw, int th, int batch, uint32_t persistent_bloc
                              hipStream_t st) {
   if (n_tiles == 0) return hipSuccess;
   const RasterLaunch g = raster_geometry(n_tiles, work, persistent_blocks, st);
-  UBS_TILE_DISPATCH(raster_bwd_t, g, records, values, ranges, views, n_views, t_ws, ncontrib,
-                    d_image, d_tfinal, l1_image, l1_target, l1_scale, grad2d, st);
+  UBS_TILE_DISPATCH(raster_bwd_t, g, grad_dirty, records, values, ranges, views, n_views, t_ws,
+                    ncontrib, d_image, d_tfinal, l1_image, l1_target, l1_scale, grad2d, st);
 }
 
 }  // namespace ubs

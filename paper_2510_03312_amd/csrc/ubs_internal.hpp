@@ -147,7 +147,9 @@ struct DevStatus {
   uint32_t sort_stalled;     // reserved (no bounded wait in the current kernels), 0
   uint32_t work_counter[3];  // persistent raster queues (fwd, bwd, spare)
   uint32_t spill;            // 1 if some tile met more records than its slot block holds
-  uint32_t _pad[6];
+  uint32_t grad_dirty;       // 1 once a backward raster has accumulated into the record
+                             // gradients since the binning zeroed the live records' rows
+  uint32_t _pad[5];
 };
 
 static_assert(offsetof(DevStatus, spill) == offsetof(ubs_status_block, spill), "spill offset");

@@ -253,7 +253,11 @@ def test_raster_only_parity_on_identical_records():
     frame.set_dparams(0, dparams)
     r.render_bwd(frame, to_dev(dimg.astype(np.float32)).view(-1, 3),
                  to_dev(dtf.astype(np.float32)).view(-1))
-    g2 = r.grad2d().cpu().numpy()
+    # the rows of live records (rho > 0); culled records' rows are not written
+    live = recs[:, 5] > 0
+    assert (d_rec[~live] == 0).all()
+    g2 = r.grad2d().cpu().numpy()[live]
+    d_rec, d_abs = d_rec[live], d_abs[live]
     for k in range(10):
         v = grad_violations(g2[:, k], d_rec[:, k], noise=d_abs[:, k])
         assert v.sum() == 0, (k, np.flatnonzero(v)[:5], g2[v, k][:5], d_rec[v, k][:5])
@@ -518,3 +522,25 @@ def test_fp32_per_primitive_math_meets_the_bars(case):
     # the float32 option keeps the pixel bar; its gradients meet 1e-2 (float32
     # loses ~cond(Sigma_q) * 2^-24 in Sigma_q^-1), the float64 default 1e-3
     assert nbad == 0 and bad == 0
+
+
+def test_second_backward_of_one_frame_gives_the_same_gradients():
+    """The binning zeroes the live records' gradient rows and the backward
+    raster marks them used: a second ubs_render_bwd of the same frame (as a
+    retained autograd graph makes) clears them first, so both passes give
+    the same gradients; and a frame binned again starts clean."""
+    from paper_2510_03312_amd import Renderer, SceneRef
+    log("[bwd] twice")
+    cfg = make_config("headline", n=20000, width=200, height=120)
+    sc = cfg["scenes"][0]
+    r = Renderer()
+    r.forward([SceneRef(to_dev(sc.params), sc.dim, sc.rot)], cfg["views"])
+    d = to_dev(np.random.default_rng(2).normal(size=(200 * 120, 3)).astype(np.float32))
+    (g1,) = r.backward(d)
+    g1 = g1.cpu().numpy()
+    (g2,) = r.backward(d)
+    g2 = g2.cpu().numpy()
+    assert grad_violations(g2, g1.astype(np.float64), rtol=1e-4, floor=1e-3).sum() == 0
+    r.forward([SceneRef(to_dev(sc.params), sc.dim, sc.rot)], cfg["views"])
+    (g3,) = r.backward(d)
+    assert grad_violations(g3.cpu().numpy(), g1.astype(np.float64), rtol=1e-4, floor=1e-3).sum() == 0
