@@ -59,7 +59,7 @@ def _oracle_records(sc, view):
             "amb_kind": orender.ambiguity_kinds(out) if amb.any() else None, "rec_f": rec_f}
 
 
-@pytest.fixture(scope="module", params=list(WORKLOADS))
+@pytest.fixture(scope="module")
 def full(request):
     from paper_2510_03312_amd import Renderer, SceneRef, split_views
     from paper_2510_03312_amd.renderer import GraphFrame, render
@@ -132,6 +132,7 @@ def _view_records(full, k):
     return full["records"][k * n:(k + 1) * n]
 
 
+@pytest.mark.parametrize("full", list(WORKLOADS), indirect=True)
 def test_full_size_sampled_records(full):
     n_views = len(full["views"])
     for k in range(n_views):
@@ -157,6 +158,7 @@ class _V:
         self.width, self.height, self.n_records = v.width, v.height, n
 
 
+@pytest.mark.parametrize("full", list(WORKLOADS), indirect=True)
 def test_full_size_binning_bit_exact(full):
     """Every key, value and range of the frame against the oracle's binning
     reference on the same float32 records."""
@@ -169,6 +171,7 @@ def test_full_size_binning_bit_exact(full):
     np.testing.assert_array_equal(full["ranges"], rg)
 
 
+@pytest.mark.parametrize("full", list(WORKLOADS), indirect=True)
 def test_full_size_sort_invariants(full):
     keys, vals, ranges, rec = full["keys"], full["vals"], full["ranges"], full["records"]
     assert np.all(keys[1:] >= keys[:-1])
@@ -184,6 +187,7 @@ def test_full_size_sort_invariants(full):
     assert np.all(vals[1:][same] > vals[:-1][same])
 
 
+@pytest.mark.parametrize("full", list(WORKLOADS), indirect=True)
 def test_full_size_sampled_pixels(full):
     n_views = len(full["views"])
     per = max(N_PIX // n_views, 50)
@@ -207,9 +211,16 @@ def test_full_size_sampled_pixels(full):
     assert flagged <= MAX_FLAGGED * total
 
 
-def test_full_size_band_gradients(full):
-    if full["dparams"] is None:
-        pytest.skip("forward-only workload")
+@pytest.mark.parametrize("full", ["headline", "cfg2", "cfg3"], indirect=True)
+def test_full_size_gradients(full):
+    """Band gradients against the oracle; for the batched frame also the
+    parameter gradient against the sum of its views rendered one per frame."""
+    _band_gradients(full)
+    if full["launch"] == "batched":
+        _batched_gradient_is_the_sum_of_single_views(full)
+
+
+def _band_gradients(full):
     sc = full["sc"]
     n = sc.params.shape[1]
     single_view = len(full["views"]) == 1
@@ -234,7 +245,7 @@ def test_full_size_band_gradients(full):
                                               rows=(y0, y1))
             g2 = g2_view[sel]
             for j in range(10):
-                v = grad_violations(g2[:, j], d_rec[sel, j], noise=d_abs[sel, j])
+                v = grad_violations(g2[:, j], d_rec[sel, j])
                 assert v.sum() == 0, (k, j, sel[np.flatnonzero(v)[:5]])
             checked += sel.size
             if not single_view:
@@ -247,24 +258,19 @@ def test_full_size_band_gradients(full):
             G[:, orender._GRAD_COLS] = d_rec[sel]
             torch.autograd.backward(out["rec"], torch.from_numpy(G), retain_graph=True)
             ref = Psub.grad.numpy()
-            noise = orender._abs_chain(Psub, out["rec"], d_abs[sel])
             gp = full["dparams"][:, sel]
             sl = opp.field_slices(sc.dim, sc.rot)
             for name in GRAD_BLOCKS:
                 s_ = sl[name]
                 if s_.stop <= s_.start:
                     continue
-                v = grad_violations(gp[s_], ref[s_], noise=noise[s_])
-                strict = grad_violations(gp[s_], ref[s_])
-                log(f"    {name}: strict-relative violations {int(strict.sum())}, "
-                    f"with the fp32 sum budget {int(v.sum())}")
+                v = grad_violations(gp[s_], ref[s_])
+                log(f"    {name}: violations {int(v.sum())}")
                 assert v.sum() == 0, name
     log(f"  checked {checked} records")
 
 
-def test_full_size_batched_gradient_is_the_sum_of_single_views(full):
-    if full["launch"] != "batched":
-        pytest.skip("single-view workload")
+def _batched_gradient_is_the_sum_of_single_views(full):
     from paper_2510_03312_amd import Renderer, SceneRef
     sc = full["sc"]
     params = to_dev(sc.params)

@@ -259,7 +259,7 @@ def test_raster_only_parity_on_identical_records():
     g2 = r.grad2d().cpu().numpy()[live]
     d_rec, d_abs = d_rec[live], d_abs[live]
     for k in range(10):
-        v = grad_violations(g2[:, k], d_rec[:, k], noise=d_abs[:, k])
+        v = grad_violations(g2[:, k], d_rec[:, k])
         assert v.sum() == 0, (k, np.flatnonzero(v)[:5], g2[v, k][:5], d_rec[v, k][:5])
 
 
@@ -293,8 +293,7 @@ def test_gradients_match_oracle(case, with_dt):
     total_bad = 0
     for name, s in _block_slices(sc.dim, sc.rot).items():
         gg, go = g["dparams"][0][s], o["dparams"][s]
-        v = grad_violations(gg, go, noise=o["dparams_noise"][s])
-        log(f"  {name}: strict-relative violations {int(grad_violations(gg, go).sum())}")
+        v = grad_violations(gg, go)
         log(f"  {name}: max|ref| {np.abs(go).max():.3g} violations {int(v.sum())}")
         for r_, c_ in list(zip(*np.nonzero(v)))[:4]:
             log(f"    row {s.start + r_} prim {c_}: gpu {gg[r_, c_]:.6g} ref {go[r_, c_]:.6g}")

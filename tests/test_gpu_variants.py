@@ -61,7 +61,7 @@ def test_variant_parity(case, variant):
         s = sl[name]
         if s.stop <= s.start:
             continue
-        v = grad_violations(g["dparams"][0][s], o["dparams"][s], noise=o["dparams_noise"][s])
+        v = grad_violations(g["dparams"][0][s], o["dparams"][s])
         if v.sum():
             log(f"  {name}: {int(v.sum())} violations")
         bad += int(v.sum())
