@@ -16,40 +16,45 @@ import torch
 from . import preprocess as pp
 from . import raster
 
-# relative bands for per-primitive decisions that fp32 may take differently
-BAND_NEAR = 1e-5     # depth vs the near plane
+# relative bands for the per-primitive decisions a renderer may take
+# differently from this float64 evaluation: the near plane and the
+# definiteness of Sigma' (float64 on both sides in the renderer's default,
+# so only rounding order separates them), o(q) against 1/255 (its scalar
+# factors are float32 there); PRIM_BANDS_F32 for a renderer whose
+# per-primitive math is float32 throughout
+BAND_NEAR = 1e-9     # depth vs the near plane
 BAND_OPACITY = raster.DEFAULT_BANDS[4]  # o(q) vs 1/255
-BAND_DET = 1e-6      # det(Sigma') / (Sigma'_00 Sigma'_11) vs 0
+BAND_DET = 1e-9      # det(Sigma') / (Sigma'_00 Sigma'_11) vs 0
+PRIM_BANDS = (BAND_NEAR, BAND_OPACITY, BAND_DET)
+PRIM_BANDS_F32 = (1e-5, 1e-4, 1e-6)
 
 # record columns that receive a compositing gradient (d_rec order)
 _GRAD_COLS = [0, 1, 2, 3, 4, 6, 7, 8, 9, 10]
 
 
-def ambiguous_records(out: dict) -> np.ndarray:
-    """Primitives whose culling decision sits within a band of a threshold."""
+def _geometry_ambiguous(out: dict, prim_bands) -> np.ndarray:
+    near, _, det_band = prim_bands
     depth = out["depth"].detach().numpy()
-    o_q = out["o_q"].detach().numpy()
     Sp = out["Sp"].detach().numpy()
     det = Sp[:, 0, 0] * Sp[:, 1, 1] - Sp[:, 0, 1] * Sp[:, 1, 0]
     scale = np.abs(Sp[:, 0, 0] * Sp[:, 1, 1]) + 1e-300
-    amb = (np.abs(depth - pp.NEAR_PLANE) <= BAND_NEAR * pp.NEAR_PLANE)
-    amb |= (np.abs(o_q * 255.0 - 1.0) <= BAND_OPACITY)
-    amb |= (np.abs(det) / scale <= BAND_DET) & (depth > pp.NEAR_PLANE)
-    return amb
+    geo = (np.abs(depth - pp.NEAR_PLANE) <= near * pp.NEAR_PLANE)
+    geo |= (np.abs(det) / scale <= det_band) & (depth > pp.NEAR_PLANE)
+    return geo
 
 
-def ambiguity_kinds(out: dict) -> np.ndarray:
+def ambiguous_records(out: dict, prim_bands=PRIM_BANDS) -> np.ndarray:
+    """Primitives whose culling decision sits within a band of a threshold."""
+    o_q = out["o_q"].detach().numpy()
+    return _geometry_ambiguous(out, prim_bands) | (np.abs(o_q * 255.0 - 1.0) <= prim_bands[1])
+
+
+def ambiguity_kinds(out: dict, prim_bands=PRIM_BANDS) -> np.ndarray:
     """uint8 per primitive for the compositing's flags: 0 unambiguous, 1 its
     culling by geometry (near plane, definiteness) is uncertain, 2 only
     o(q) against 1/255 is (see raster.c)."""
-    depth = out["depth"].detach().numpy()
-    Sp = out["Sp"].detach().numpy()
-    det = Sp[:, 0, 0] * Sp[:, 1, 1] - Sp[:, 0, 1] * Sp[:, 1, 0]
-    scale = np.abs(Sp[:, 0, 0] * Sp[:, 1, 1]) + 1e-300
-    geo = (np.abs(depth - pp.NEAR_PLANE) <= BAND_NEAR * pp.NEAR_PLANE)
-    geo |= (np.abs(det) / scale <= BAND_DET) & (depth > pp.NEAR_PLANE)
-    kind = np.where(ambiguous_records(out), 2, 0).astype(np.uint8)
-    kind[geo] = 1
+    kind = np.where(ambiguous_records(out, prim_bands), 2, 0).astype(np.uint8)
+    kind[_geometry_ambiguous(out, prim_bands)] = 1
     return kind
 
 
@@ -78,12 +83,15 @@ def _amb_records(out: dict, amb: np.ndarray, rec: np.ndarray) -> np.ndarray:
 def render(params: np.ndarray, dim: int, rot: int, view, *, d_image: Optional[np.ndarray] = None,
            d_tfinal: Optional[np.ndarray] = None, l1_target: Optional[np.ndarray] = None,
            rows=None, bands=raster.DEFAULT_BANDS, record_f32: bool = False,
-           variant: tuple = ()):
+           variant: tuple = (), prim_bands=PRIM_BANDS):
     """Render one view in float64.
 
     params: [F][n] (any float dtype; promoted to float64).  If ``d_image``
     (or ``l1_target``: L1-mean loss against it, sign(0) = 0) is given, also
     returns ``dparams`` [F][n].
+
+    ``prim_bands``: (near plane, opacity, definiteness) bands of the
+    primitives whose culling is counted as ambiguous.
 
     ``record_f32``: composite from the screen-space records rounded to
     float32, the precision the renderer's record format fixes, instead of
@@ -98,10 +106,11 @@ def render(params: np.ndarray, dim: int, rot: int, view, *, d_image: Optional[np
     rec = out["rec"].detach().numpy()
     if record_f32:
         rec = rec.astype(np.float32).astype(np.float64)
-    amb = ambiguous_records(out)
+    amb = ambiguous_records(out, prim_bands)
     rec_f = _amb_records(out, amb, rec) if amb.any() else rec
     W, H = view.width, view.height
-    img, tf, nc, fl = raster.render_fwd(rec_f, W, H, amb=ambiguity_kinds(out) if amb.any() else None,
+    img, tf, nc, fl = raster.render_fwd(rec_f, W, H,
+                                        amb=ambiguity_kinds(out, prim_bands) if amb.any() else None,
                                         rows=rows, bands=bands)
     res = {"image": img, "t_final": tf, "ncontrib": nc, "flags": fl, "rec": rec,
            "valid": out["valid"].numpy(), "amb": amb, "out": out}

@@ -15,6 +15,7 @@ from _gpu_common import (GRAD_BLOCKS, bin_reference, compare_images, gpu_ready, 
                          grad_violations, log, oracle_view, to_dev)
 from oracle import preprocess as opp
 from oracle import raster as oraster
+from oracle import render as opp_render
 from synth import look_at_view, make_config, make_elongated_records, make_splat_records, make_view
 
 pytestmark = [pytest.mark.gpu,
@@ -502,11 +503,11 @@ def test_fp32_per_primitive_math_meets_the_bars(case):
     log(f"[fp32 pre] {case}")
     cfg = _cfg(case)
     view = cfg["views"][0]
-    o0 = oracle_view(cfg, 0)
+    o0 = oracle_view(cfg, 0, prim_bands=opp_render.PRIM_BANDS_F32)
     ok = o0["flags"] == 0
     rng = np.random.default_rng(4)
     dimg = rng.normal(size=(view.height, view.width, 3)) * ok[..., None] / math.sqrt(ok.size)
-    o = oracle_view(cfg, 0, d_image=dimg)
+    o = oracle_view(cfg, 0, d_image=dimg, prim_bands=opp_render.PRIM_BANDS_F32)
     g = gpu_render(cfg, Tuning(flags=UBS_TUNE_PRE_FP32), want_grad=True, d_images=[dimg])
     err, nflag, nbad = compare_images(g["images"][0], o["image"], o["flags"], 1e-4)
     log(f"  pixels: max err {err:.3g}, bad {nbad}")
