@@ -99,21 +99,21 @@ __device__ __forceinline__ void raster_fwd_tile(
   // T: transmittance; a pixel that has stopped keeps it negated, so that
   // every later record fails its T (1 - alpha) >= 1e-4 test (instead of the
   // pixel's state being tested on every record); |T| is the final value
+  // (pixels outside the image start stopped)
   float T[PPL], cr[PPL], cg[PPL], cb[PPL];
   uint32_t last[PPL];
-  uint32_t done = 0;   // bit k: pixel k has stopped (or lies outside the image)
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
-    T[k] = 1.0f; cr[k] = cg[k] = cb[k] = 0.0f; last[k] = 0;
-    if (px >= V.W || py0 + k * RSTEP >= V.H) {
-      done |= 1u << k;
-      T[k] = -1.0f;
-    }
+    T[k] = (px >= V.W || py0 + k * RSTEP >= V.H) ? -1.0f : 1.0f;
+    cr[k] = cg[k] = cb[k] = 0.0f; last[k] = 0;
   }
-  constexpr uint32_t kAll = (PPL == 32) ? 0xffffffffu : ((1u << PPL) - 1u);
   const uint32_t start = ranges[2 * size_t(tile)], end = ranges[2 * size_t(tile) + 1];
   for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
-    if (__ballot(done != kAll) == 0ull) break;
+    // the tile is finished once every pixel has stopped (checked per batch)
+    bool running = false;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) running = running || T[k] >= 0.0f;
+    if (__ballot(running) == 0ull) break;
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < PER_LANE; ++m) {
@@ -126,7 +126,6 @@ __device__ __forceinline__ void raster_fwd_tile(
       }
     }
     __syncthreads();
-    if (done == kAll) continue;
     const int nb = int(min(uint32_t(BATCH), end - b0));
     for (int j = 0; j < nb; ++j) {
       const float4 g0 = s0[j], g1 = s1[j], g2 = s2[j];
@@ -143,17 +142,17 @@ __device__ __forceinline__ void raster_fwd_tile(
         const float alpha = fminf(kAlphaMax, sigma);
         const float test = T[k] * (1.0f - alpha);
         const bool hit = alpha >= kAlphaMin;
-        const bool con = hit && test >= kTStop;
-        const bool stop = hit && !(test >= kTStop);
-        done |= stop ? (1u << k) : 0u;
+        const bool pass = test >= kTStop;
+        const bool con = hit && pass;
         const float w = con ? alpha * T[k] : 0.0f;
         cr[k] += g2.x * w;
         cg[k] += g2.y * w;
         cb[k] += g2.z * w;
-        T[k] = con ? test : (stop ? -fabsf(T[k]) : T[k]);
+        // a hit that fails the stop test stops the pixel (T kept negated)
+        const float tn = pass ? test : -fabsf(T[k]);
+        T[k] = hit ? tn : T[k];
         last[k] = con ? b0 - start + uint32_t(j) + 1u : last[k];
       }
-      if (done == kAll) break;
     }
   }
 #pragma unroll
@@ -263,8 +262,9 @@ __device__ __forceinline__ void raster_bwd_tile(
   const float fx = float(px) + 0.5f;
   const uint32_t start = ranges[2 * size_t(tile)];
   // gTf: d loss / d T_final times T_final (the transmittance gradient enters
-  // every record's d alpha as - gTf / (1 - alpha))
-  float T[PPL], Sr[PPL], Sg[PPL], Sb[PPL], gR[PPL], gG[PPL], gB[PPL], gTf[PPL];
+  // every record's d alpha as - gTf / (1 - alpha)); D: the pixel's colour
+  // gradient dotted with the colour composited behind the current record
+  float T[PPL], D[PPL], gR[PPL], gG[PPL], gB[PPL], gTf[PPL];
   uint32_t last[PPL];
   uint32_t lane_max = 0;
 #pragma unroll
@@ -291,10 +291,11 @@ __device__ __forceinline__ void raster_bwd_tile(
       }
     }
     T[k] = Tf;
-    Sr[k] = Sg[k] = Sb[k] = 0.0f;
+    D[k] = 0.0f;
     lane_max = max(lane_max, last[k]);
   }
-  const uint32_t span = wave_max_u32(lane_max);
+  // (wavefront-uniform: the batch loop runs on scalar counters)
+  const uint32_t span = __builtin_amdgcn_readfirstlane(wave_max_u32(lane_max));
   for (uint32_t hi = span; hi > 0;) {
     const uint32_t lo = hi > uint32_t(BATCH) ? hi - uint32_t(BATCH) : 0u;
     const uint32_t cnt = hi - lo;
@@ -340,17 +341,18 @@ __device__ __forceinline__ void raster_bwd_tile(
         const bool con = fminf(kAlphaMax, sigma0) >= kAlphaMin;
         any = any || con;
         const float alpha = con ? fminf(kAlphaMax, sigma0) : 0.0f;
-        const float sigma = (con && sigma0 < kAlphaMax) ? sigma0 : 0.0f;
+        // sigma where alpha follows it (below the clamp), else 0
+        const float sigma = alpha < kAlphaMax ? alpha : 0.0f;
         const float ioma = fast_rcp(1.0f - alpha);
         const float Ti = con ? T[k] * ioma : T[k];
         const float w = alpha * Ti;
         a_r += gR[k] * w;
         a_g += gG[k] * w;
         a_b += gB[k] * w;
-        // colour in front of the record minus the colour behind it; the
-        // colour behind updates as S += alpha (c - S)
-        const float er = g2.x - Sr[k], eg = g2.y - Sg[k], eb = g2.z - Sb[k];
-        const float dot = gR[k] * er + gG[k] * eg + gB[k] * eb;
+        // g . (c - S): the colour gradient g dotted with the record's colour
+        // minus the colour S composited behind it; S updates as
+        // S += alpha (c - S), so D = g . S as D += alpha dot
+        const float dot = (gR[k] * g2.x + gG[k] * g2.y + gB[k] * g2.z) - D[k];
         const float dalpha = HAS_DT ? Ti * dot - gTf[k] * ioma : Ti * dot;
         const float sd = sigma * dalpha;
         a_o += sd;
@@ -360,9 +362,7 @@ __device__ __forceinline__ void raster_bwd_tile(
         const float qy = q * dy;
         a_dry += qy;
         a_dryy += qy * dy;
-        Sr[k] += alpha * er;
-        Sg[k] += alpha * eg;
-        Sb[k] += alpha * eb;
+        D[k] += alpha * dot;
         T[k] = Ti;
       }
       if (__ballot(any) == 0ull) continue;
