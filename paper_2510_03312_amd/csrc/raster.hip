@@ -19,6 +19,8 @@
 // Both passes take every per-pixel decision (support test, skip, stop)
 // through the same inline functions, so the backward pass visits exactly
 // the contributors the forward pass used.
+#include <type_traits>
+
 #include "ubs_internal.hpp"
 
 namespace ubs {
@@ -163,7 +165,8 @@ __device__ __forceinline__ void raster_fwd_tile(
       image[3 * pix] = cr[k];
       image[3 * pix + 1] = cg[k];
       image[3 * pix + 2] = cb[k];
-      t_ws[pix] = fabsf(T[k]);
+      // (the internal copy keeps the sign: negative for a pixel that stopped)
+      t_ws[pix] = T[k];
       if (t_user) t_user[pix] = fabsf(T[k]);
       ncontrib[pix] = last[k];
     }
@@ -234,6 +237,11 @@ __device__ __forceinline__ void opaque_zero2(float& a, float& b) {
 }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = min(x, uint32_t(__shfl_xor(int(x), o, 64)));
+  return x;
+}
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x = max(x, uint32_t(__shfl_xor(int(x), o, 64)));
@@ -266,7 +274,7 @@ __device__ __forceinline__ void raster_bwd_tile(
   // gradient dotted with the colour composited behind the current record
   float T[PPL], D[PPL], gR[PPL], gG[PPL], gB[PPL], gTf[PPL];
   uint32_t last[PPL];
-  uint32_t lane_max = 0;
+  uint32_t lane_max = 0, lane_stop = 0xffffffffu;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int py = py0 + k * RSTEP;
@@ -276,6 +284,10 @@ __device__ __forceinline__ void raster_bwd_tile(
       const size_t pix = size_t(V.pix_base) + size_t(py) * V.W + px;
       Tf = t_ws[pix];
       last[k] = ncontrib[pix];
+      if (Tf < 0.0f) {   // the pixel stopped
+        Tf = -Tf;
+        lane_stop = min(lane_stop, last[k]);
+      }
       if (d_image) {
         gR[k] = d_image[3 * pix];
         gG[k] = d_image[3 * pix + 1];
@@ -296,6 +308,11 @@ __device__ __forceinline__ void raster_bwd_tile(
   }
   // (wavefront-uniform: the batch loop runs on scalar counters)
   const uint32_t span = __builtin_amdgcn_readfirstlane(wave_max_u32(lane_max));
+  // Records at or beyond a pixel's last contributor contribute nothing to it
+  // unless the pixel stopped (its own alpha test fails there otherwise), so
+  // only records at or beyond the smallest last contributor of a stopped
+  // pixel need the position test.
+  const uint32_t stop_min = __builtin_amdgcn_readfirstlane(wave_min_u32(lane_stop));
   for (uint32_t hi = span; hi > 0;) {
     const uint32_t lo = hi > uint32_t(BATCH) ? hi - uint32_t(BATCH) : 0u;
     const uint32_t cnt = hi - lo;
@@ -311,7 +328,10 @@ __device__ __forceinline__ void raster_bwd_tile(
       }
     }
     __syncthreads();
-    for (int j = int(cnt) - 1; j >= 0; --j) {
+    // one record: the lane's pixel sums, then their wavefront totals added to
+    // the record's gradient row (CHECK: test each pixel's last contributor)
+    auto record = [&](auto check, int j) {
+      constexpr bool CHECK = decltype(check)::value;
       const uint32_t pos = lo + uint32_t(j);
       const float4 g0 = s0[j], g1 = s1[j], g2 = s2[j];
       const float dx = fx - g0.x;
@@ -327,7 +347,6 @@ __device__ __forceinline__ void raster_bwd_tile(
       opaque_zero2(a_b, a_o);
       opaque_zero2(a_be, a_dr);
       opaque_zero2(a_dry, a_dryy);
-      bool any = false;
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
         const float dy = float(py0 + k * RSTEP) + 0.5f - g0.y;
@@ -335,16 +354,17 @@ __device__ __forceinline__ void raster_bwd_tile(
         // one branch per pixel: the rare cases inside it (alpha below
         // 1/255 at the support's rim, sigma at the 0.99 clamp) are taken
         // by zeroing alpha or sigma, which makes their updates no-ops
-        if (!(pos < last[k] && r <= g1.y)) continue;
+        if (!((!CHECK || pos < last[k]) && r <= g1.y)) continue;
         float l2;
         const float sigma0 = eval_sigma(r, g1.z, g1.w, &l2);
         const bool con = fminf(kAlphaMax, sigma0) >= kAlphaMin;
-        any = any || con;
         const float alpha = con ? fminf(kAlphaMax, sigma0) : 0.0f;
         // sigma where alpha follows it (below the clamp), else 0
         const float sigma = alpha < kAlphaMax ? alpha : 0.0f;
+        // (alpha = 0 gives ioma = 1 exactly: the hardware reciprocal is exact
+        // on powers of two, so T passes unchanged)
         const float ioma = fast_rcp(1.0f - alpha);
-        const float Ti = con ? T[k] * ioma : T[k];
+        const float Ti = T[k] * ioma;
         const float w = alpha * Ti;
         a_r += gR[k] * w;
         a_g += gG[k] * w;
@@ -365,8 +385,8 @@ __device__ __forceinline__ void raster_bwd_tile(
         D[k] += alpha * dot;
         T[k] = Ti;
       }
-      if (__ballot(any) == 0ull) continue;
-      // the record's pixel sums (P, Q, U, V, E, A_o, A_b, colour): the
+      // the record's pixel sums (a record none of whose pixels contribute,
+      // a few in a hundred thousand, adds zeros) (P, Q, U, V, E, A_o, A_b, colour): the
       // per-primitive adjoint turns them into record-field gradients
       float gv[kGradFloats];
       gv[0] = dx * a_dr;
@@ -411,6 +431,11 @@ __device__ __forceinline__ void raster_bwd_tile(
         atomicAdd(g + 4 + sub, t3[1]);
         if ((row & 1) == 0) atomicAdd(g + 8 + (row >> 1), t3[2]);
       }
+    };
+    if (hi <= stop_min) {
+      for (int j = int(cnt) - 1; j >= 0; --j) record(std::false_type{}, j);
+    } else {
+      for (int j = int(cnt) - 1; j >= 0; --j) record(std::true_type{}, j);
     }
     hi = lo;
   }

@@ -230,12 +230,40 @@ def test_render_forward_matches_oracle(case):
     assert nflag <= 0.001 * o["flags"].size     # observed: at most 2 of 32,400
 
 
-def test_raster_only_parity_on_identical_records():
-    """Identical float32 records on both sides isolate the compositing."""
-    log("[fwd] raster only")
-    W, H, n = 160, 120, 1500
+def _stopped_pixels(recs, W, H):
+    """Pixels whose compositing stops (a record would take T below 1e-4),
+    by a plain float64 replay in (depth, index) order."""
+    order = np.lexsort((np.arange(len(recs)), recs[:, 11].astype(np.float64)))
+    yy, xx = np.mgrid[0:H, 0:W] + 0.5
+    T = np.ones((H, W))
+    stopped = np.zeros((H, W), bool)
+    for i in order:
+        r = recs[i].astype(np.float64)
+        if not r[5] > 0:
+            continue
+        dx, dy = xx - r[0], yy - r[1]
+        q = r[2] * dx * dx + 2 * r[3] * dx * dy + r[4] * dy * dy
+        a = np.where(q <= r[5], np.minimum(0.99, r[6] * np.clip(1 - q, 0, None) ** r[7]), 0.0)
+        hit = (a >= 1 / 255) & ~stopped
+        test = T * (1 - a)
+        stop = hit & (test < 1e-4)
+        stopped |= stop
+        T = np.where(hit & ~stop, test, T)
+    return int(stopped.sum())
+
+
+@pytest.mark.parametrize("n", [1500, 6000])
+def test_raster_only_parity_on_identical_records(n):
+    """Identical float32 records on both sides isolate the compositing; at
+    6000 records a tenth of the pixels stop (T would fall below 1e-4), so
+    the backward pass's test of each pixel's last contributor is exercised."""
+    log(f"[fwd] raster only, {n} records")
+    W, H = 160, 120
     cfg = make_config("cfg0", n=n, width=W, height=H)
     recs = make_splat_records(n, W, H, seed=7, max_extent=25.0)
+    n_stop = _stopped_pixels(recs, W, H)
+    log(f"  stopped pixels {n_stop}")
+    assert n < 6000 or n_stop >= 1000
     r, frame, K, keys, vals, ranges = _inject_and_sort(cfg, recs)
     img = torch.empty((W * H, 3), device="cuda")
     tf = torch.empty((W * H,), device="cuda")
