@@ -44,16 +44,16 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 #            dy, r = A + dy (B + c dy), support test                      4
 #   support  r <= rho: 1 - r, log2, fma with beta and log2 o, exp2,
 #            min 0.99, alpha test                                         12
-#   contrib  alpha >= 1/255: 1 - alpha, rcp, T/(1-alpha), weight, three
-#            colour-gradient sums (6), c - S shared by d alpha and the
-#            running colour S += alpha (c - S) (3 + 3)                    20
-#   grad     sigma < 0.99 as well: d alpha = T/(1-alpha) g.(c - S) (4),
-#            s = sigma d alpha, opacity and beta sums, rcp of 1 - r and
-#            s/(1 - r), the three moment sums                             13
+#   contrib  alpha >= 1/255: 1 - alpha, rcp (4), T/(1-alpha), weight
+#            alpha T, three colour-gradient sums (3), g.c (3), g.c - g.S
+#            with g.S kept per pixel, g.S += alpha (g.c - g.S)             15
+#   grad     sigma < 0.99 as well: d alpha = T (g.c - g.S), s = sigma
+#            d alpha, opacity and beta sums, rcp of 1 - r (4), s/(1 - r),
+#            the three moment sums (4)                                    13
 #   pair     per (tile, record): dx and the column terms of the tile's 16
 #            pixel columns (4 each), 1/o, the ten sums turned into the
 #            record-field gradients (14)                                  64 + 4 + 14
-BWD_OPS = {"eval": 4, "support": 12, "contrib": 20, "grad": 13, "pair": 82}
+BWD_OPS = {"eval": 4, "support": 12, "contrib": 15, "grad": 13, "pair": 82}
 # Forward raster: eval and support as above; contrib: T (1 - alpha) and its
 # stop test, weight alpha T, three colour FMAs, the contributor count (8);
 # pair: the column terms (64) and log2 o (4).
