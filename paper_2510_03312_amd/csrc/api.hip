@@ -190,8 +190,9 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
     d.list_base = int64_t(n_list);
     n_prims += uint64_t(S.n);
     n_list += uint64_t(kKeptLists) * kept_list_cap(S.n);
-    n_grad_compact = n_grad_compact > uint64_t(d.F) * uint64_t(S.n) ? n_grad_compact
-                                                                       : uint64_t(d.F) * uint64_t(S.n);
+    // the adjoint's compacted gradients: F rows of one column per kept-list entry
+    const uint64_t n_compact = uint64_t(d.F) * kKeptLists * kept_list_cap(S.n);
+    n_grad_compact = n_grad_compact > n_compact ? n_grad_compact : n_compact;
     if (n_prims > 0x7fffffffull) return UBS_ERR_UNSUPPORTED;
     ds->push_back(d);
   }

@@ -131,10 +131,10 @@ __device__ __forceinline__ void record_gradient_from_sums(const float* __restric
   g[6] = g[6] * 0.69314718f;
 }
 
-// Thread t runs the adjoint of the t-th kept primitive (in the concatenation
-// of the kept lists) and writes its gradient to column t of the compacted
-// [F][n] buffer (coalesced); scatter_dparams_kernel moves it to the
-// primitive's column.
+// Thread t runs the adjoint of the primitive at entry t of the kept lists
+// (list t / cap) and writes its gradient to column t of the compacted
+// [F][kKeptLists cap] buffer (coalesced); scatter_dparams_kernel moves it to
+// the primitive's column.
 template <typename T, int C, int ROT>
 __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int scene,
                                                              const DevView* __restrict__ views,
@@ -143,19 +143,12 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int sce
                                                              float* __restrict__ grad2d,
                                                              LiveIn kept,
                                                              float* __restrict__ compact) {
-  const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  uint32_t total;
-  const uint32_t excl = kept_list_prefix(kept.count, &total);
-  // the list holding entry t: the last k with excl(k) <= t (binary search
-  // over the lanes' prefixes, every lane active)
-  const uint32_t tt = t < int64_t(total) ? uint32_t(t) : 0u;
-  int lo = 0;
-#pragma unroll
-  for (int step = 32; step > 0; step >>= 1)
-    if (uint32_t(__shfl(int(excl), lo + step, 64)) <= tt) lo += step;
-  const uint32_t start = uint32_t(__shfl(int(excl), lo, 64));
-  if (t >= int64_t(total)) return;
-  const int64_t i = kept.list[size_t(lo) * kept.cap + (tt - start)];
+  // thread t takes entry t % cap of kept list t / cap (cap is a multiple of
+  // the workgroup size, so a workgroup stays inside one list)
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t lo = t / kept.cap, pos = t - lo * kept.cap;
+  if (pos >= kept.count[lo]) return;
+  const int64_t i = kept.list[t];
   Raw<C, ROT> r;
   load_raw<C, ROT>(S.params, S.n, i, r);
   Geo<T, C, ROT> g;
@@ -183,38 +176,49 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int sce
   constexpr int F = param_rows(C, ROT).F;
   float out[F];
   geo_backward<T, C, ROT>(r, g, G, out);
+  const int64_t stride = int64_t(kKeptLists) * kept.cap;
 #pragma unroll
-  for (int k = 0; k < F; ++k) compact[int64_t(k) * S.n + t] = out[k];
+  for (int k = 0; k < F; ++k) compact[int64_t(k) * stride + t] = out[k];
 }
 
-// dparams[k, i] = compact[k, j(i)] for kept primitives (j: position in the
-// concatenated kept lists), 0 otherwise.  One
-// primitive per thread; the rows go in chunks whose loads are all issued
-// before their stores, so a wavefront waits for memory once per chunk
-// rather than once per row.
+// dparams[k, i] = compact[k, j(i)] for kept primitives (j: the column of
+// their kept-list entry), 0 otherwise.  VEC primitives per thread (4: one
+// 16-byte store per row, for rows that start 16-byte aligned); the rows go
+// in chunks whose loads are all issued before their stores, so a wavefront
+// waits for memory once per chunk rather than once per row.
 constexpr int kScatterChunk = 9;
 
+template <int VEC>
 __global__ void __launch_bounds__(256) scatter_dparams_kernel(DevScene S, LiveIn kept,
                                                               const float* __restrict__ compact) {
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  // the workgroup's 256 primitives are preprocess workgroup blockIdx.x's
-  uint32_t total;
-  const uint32_t excl = kept_list_prefix(kept.count, &total);
-  const uint32_t start = uint32_t(__shfl(int(excl), int(blockIdx.x % kKeptLists), 64));
-  if (i >= S.n) return;
-  const bool is_live = kept.flags[i] != 0;
-  const int64_t j = is_live ? int64_t(start) + int64_t(kept.pos[i]) : 0;
+  const int64_t i0 = (int64_t(blockIdx.x) * 256 + threadIdx.x) * VEC;
+  if (i0 >= S.n) return;
+  const int64_t stride = int64_t(kKeptLists) * kept.cap;
+  // (a primitive's list: that of its preprocess workgroup of 256; the VEC
+  // primitives of a thread share it)
+  const int64_t list_base = int64_t((i0 / 256) % kKeptLists) * kept.cap;
+  bool live[VEC];
+  int64_t j[VEC];
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) {
+    live[q] = i0 + q < S.n && kept.flags[i0 + q] != 0;
+    j[q] = live[q] ? list_base + int64_t(kept.pos[i0 + q]) : 0;
+  }
   for (int k0 = 0; k0 < S.F; k0 += kScatterChunk) {
-    float v[kScatterChunk];
+    float v[kScatterChunk][VEC];
 #pragma unroll
-    for (int q = 0; q < kScatterChunk; ++q) {
-      const int k = k0 + q;
-      v[q] = (is_live && k < S.F) ? compact[int64_t(k) * S.n + j] : 0.0f;
-    }
+    for (int c = 0; c < kScatterChunk; ++c)
 #pragma unroll
-    for (int q = 0; q < kScatterChunk; ++q) {
-      const int k = k0 + q;
-      if (k < S.F) store_stream(&S.dparams[int64_t(k) * S.n + i], v[q]);
+      for (int q = 0; q < VEC; ++q)
+        v[c][q] = (live[q] && k0 + c < S.F) ? compact[int64_t(k0 + c) * stride + j[q]] : 0.0f;
+#pragma unroll
+    for (int c = 0; c < kScatterChunk; ++c) {
+      if (k0 + c >= S.F) break;
+      float* row = S.dparams + int64_t(k0 + c) * S.n;
+      if constexpr (VEC == 4)
+        store_stream(reinterpret_cast<float4*>(row + i0), make_float4(v[c][0], v[c][1], v[c][2], v[c][3]));
+      else
+        store_stream(row + i0, v[c][0]);
     }
   }
 }
@@ -233,10 +237,17 @@ template <typename T, int C, int ROT>
 static hipError_t pre_bwd_t(const DevScene& S, int scene, const DevView* views, int n_views,
                             const float* records, float* grad2d, LiveIn kept, float* compact,
                             hipStream_t st) {
-  const unsigned blocks = unsigned((S.n + 255) / 256);
+  // one thread per entry of the kKeptLists lists of cap entries
+  const unsigned blocks = unsigned(uint64_t(kKeptLists) * kept.cap / 256);
   hipLaunchKernelGGL((preprocess_bwd_kernel<T, C, ROT>), dim3(blocks), dim3(256), 0, st, S, scene,
                      views, n_views, records, grad2d, kept, compact);
-  hipLaunchKernelGGL(scatter_dparams_kernel, dim3(blocks), dim3(256), 0, st, S, kept, compact);
+  // 16-byte stores when every row of dparams starts 16-byte aligned
+  if (S.n % 4 == 0 && reinterpret_cast<uintptr_t>(S.dparams) % 16 == 0)
+    hipLaunchKernelGGL(scatter_dparams_kernel<4>, dim3(unsigned((S.n / 4 + 255) / 256)), dim3(256),
+                       0, st, S, kept, compact);
+  else
+    hipLaunchKernelGGL(scatter_dparams_kernel<1>, dim3(unsigned((S.n + 255) / 256)), dim3(256), 0,
+                       st, S, kept, compact);
   return hipGetLastError();
 }
 

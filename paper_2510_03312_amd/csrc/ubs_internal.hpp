@@ -97,10 +97,11 @@ __host__ __device__ constexpr bool dim_ok(int dim) {
 // the adjoint.  The kept primitives of preprocess workgroup b (256
 // primitives) go to list b mod kKeptLists, each list holding up to `cap`
 // entries (cap = kept_list_cap(n)), with `count` entries per list; pos is a
-// kept primitive's index inside its list.  A primitive's position in the
-// concatenation of the lists, which the adjoint's compacted buffer uses, is
-// its pos plus the counts of the lists before its own.  (Several counters
-// spread the workgroups' reserving atomics over several addresses.)
+// kept primitive's index inside its list.  The adjoint runs one thread per
+// list entry, entry e of list l being column l cap + e of its compacted
+// gradient buffer (the columns past a list's count are unused).  (Several
+// counters spread the workgroups' reserving atomics over several
+// addresses.)
 constexpr uint32_t kKeptLists = 64;
 __host__ __device__ constexpr uint32_t kept_list_cap(int64_t n) {
   return uint32_t(((n + 255) / 256 + kKeptLists - 1) / kKeptLists) * 256u;
@@ -120,23 +121,6 @@ struct LiveIn {
   uint32_t cap;
 };
 
-// Within a wavefront: lane k < kKeptLists holds the exclusive prefix of the
-// kept-list counts at k (kKeptLists == 64: one list per lane); also returns
-// the total in *total.
-__device__ __forceinline__ uint32_t kept_list_prefix(const uint32_t* __restrict__ count,
-                                                     uint32_t* total) {
-  const int lane = threadIdx.x & 63;
-  const uint32_t c = count[lane];
-  uint32_t x = c;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  *total = uint32_t(__shfl(int(x), 63, 64));
-  return x - c;
-}
-static_assert(kKeptLists == 64, "one kept list per lane of a wavefront");
 
 // Status block, mirrors ubs_status_block.
 struct DevStatus {
