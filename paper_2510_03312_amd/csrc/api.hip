@@ -24,7 +24,7 @@ hipError_t launch_bin_count(const float* records, const DevView* views, int n_vi
                             uint32_t slot_cap, DevStatus* status, float* grad2d, hipStream_t st);
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
                        DevStatus* status, unsigned long long capacity, hipStream_t st,
-                       unsigned long long* total_out);
+                       unsigned long long* total_out, uint32_t* order);
 hipError_t launch_bin_emit(const float* records, const DevView* views, int n_views,
                            uint32_t n_records, const uint32_t* hit_mask, const uint32_t* big_list,
                            const uint32_t* big_count, uint32_t* tile_cursor,
@@ -38,13 +38,15 @@ hipError_t launch_tile_sort(unsigned long long* comp, const unsigned long long* 
                             uint32_t* n_big_tiles, hipStream_t st);
 hipError_t launch_raster_fwd(int tw, int th, int batch, uint32_t persistent_blocks,
                              uint32_t* work, const float* records, const uint32_t* values,
-                             const uint32_t* ranges, const DevView* views, int n_views,
+                             const uint32_t* ranges, const uint32_t* order,
+                             const DevView* views, int n_views,
                              uint32_t n_tiles, float* image, float* t_ws, float* t_user,
                              uint32_t* ncontrib, hipStream_t st);
 hipError_t launch_raster_bwd(int tw, int th, int batch, uint32_t persistent_blocks,
                              uint32_t* work, uint32_t* grad_dirty, const float* records,
                              const uint32_t* values,
-                             const uint32_t* ranges, const DevView* views, int n_views,
+                             const uint32_t* ranges, const uint32_t* order,
+                             const DevView* views, int n_views,
                              uint32_t n_tiles, const float* t_ws, const uint32_t* ncontrib,
                              const float* d_image, const float* d_tfinal, const float* l1_image,
                              const float* l1_target, float l1_scale, float* grad2d,
@@ -254,6 +256,7 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.pub.off_records = take(uint64_t(kRecFloats) * 4 * n_rec);
   l.off_tile_counts = take(4 * (n_tiles + 2));
   l.off_big_tiles = take(4 * n_tiles);
+  l.off_tile_order = take(4 * n_tiles);
   l.off_tile_cursor = take(4 * n_tiles);
   l.off_hit_mask = take(4 * n_rec);
   l.off_big_list = take(4 * n_rec);
@@ -419,7 +422,8 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
   stage_mark(frame, UBS_STAGE_BIN_COUNT, 1, s);
   stage_mark(frame, UBS_STAGE_SCAN, 0, s);
   // segment starts of the tiles; the total sets pairs_needed and overflow
-  UBS_HIP(launch_scan(tile_counts, n_tiles, sums, tile_cursor, status, cap, s, nullptr));
+  UBS_HIP(launch_scan(tile_counts, n_tiles, sums, tile_cursor, status, cap, s, nullptr,
+                      at<uint32_t>(ws, L.off_tile_order)));
   stage_mark(frame, UBS_STAGE_SCAN, 1, s);
   stage_mark(frame, UBS_STAGE_BIN_EMIT, 0, s);
   UBS_HIP(launch_bin_emit(records, views, frame->n_views, n_rec, hit_mask, big_list, big_count,
@@ -448,6 +452,7 @@ ubs_status ubs_render_fwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes, f
   UBS_HIP(launch_raster_fwd(L.tile_w, L.tile_h, frame->tuning.batch_depth, persistent_blocks(frame),
                             &status->work_counter[0], at<float>(ws, L.pub.off_records),
                             at<uint32_t>(ws, L.pub.off_values), at<uint32_t>(ws, L.pub.off_ranges),
+                            at<uint32_t>(ws, L.off_tile_order),
                             at<DevView>(ws, L.off_views), frame->n_views, uint32_t(L.pub.n_tiles),
                             image, at<float>(ws, L.off_tfinal_ws), t_final,
                             at<uint32_t>(ws, L.pub.off_ncontrib), s));
@@ -483,6 +488,7 @@ ubs_status ubs_render_bwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
                             &status->work_counter[1], &status->grad_dirty,
                             at<float>(ws, L.pub.off_records),
                             at<uint32_t>(ws, L.pub.off_values), at<uint32_t>(ws, L.pub.off_ranges),
+                            at<uint32_t>(ws, L.off_tile_order),
                             views, frame->n_views, uint32_t(L.pub.n_tiles),
                             at<float>(ws, L.off_tfinal_ws), at<uint32_t>(ws, L.pub.off_ncontrib),
                             d_image, d_t_final, l1_image, l1_target, l1_scale, grad2d, s));

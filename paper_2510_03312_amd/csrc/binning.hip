@@ -536,14 +536,85 @@ hipError_t launch_bin_count(const float* records, const DevView* views, int n_vi
 // three); same outputs as the three-kernel scan.
 constexpr uint32_t kSingleScanMax = 16u * kScanTile;
 constexpr int kSingleThreads = 1024;
+
+// Order in which the rasters take the tiles: by pair count, largest first
+// (ties in no particular order), so that the last tiles a launch hands out
+// are small ones and the SIMDs finish together.  A counting sort of the
+// tiles on min(count, kOrderBins - 1) by one workgroup of kOrderBins threads.
+constexpr int kOrderBins = 1024;
+constexpr int kOrderPer = 8;   // tiles per thread per round (their loads issued together)
+
+__device__ __forceinline__ void order_tiles_by_count(const uint32_t* __restrict__ counts,
+                                                     uint32_t n, uint32_t* __restrict__ order,
+                                                     uint32_t* bins, uint32_t* wave_tot) {
+  const uint32_t tid = threadIdx.x;
+  // bin kOrderBins - 1 - min(count, kOrderBins - 1): an ascending scan of
+  // the bins puts the longest tiles first
+  auto bins_of = [&](uint32_t base, uint32_t* b) {
+    uint32_t c[kOrderPer];
+#pragma unroll
+    for (int q = 0; q < kOrderPer; ++q) {
+      const uint32_t t = base + uint32_t(q) * kOrderBins + tid;
+      c[q] = t < n ? counts[t] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kOrderPer; ++q)
+      b[q] = uint32_t(kOrderBins - 1) - min(c[q], uint32_t(kOrderBins - 1));
+  };
+  bins[tid] = 0u;
+  __syncthreads();
+  for (uint32_t base = 0; base < n; base += kOrderBins * kOrderPer) {
+    uint32_t b[kOrderPer];
+    bins_of(base, b);
+#pragma unroll
+    for (int q = 0; q < kOrderPer; ++q)
+      if (base + uint32_t(q) * kOrderBins + tid < n) atomicAdd(&bins[b[q]], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of the bins: within wavefronts, then over their totals
+  const int lane = int(tid & 63), wave = int(tid >> 6);
+  const uint32_t c = bins[tid];
+  uint32_t x = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wave_tot[wave] = x;
+  __syncthreads();
+  uint32_t wbase = 0;
+  for (int w = 0; w < wave; ++w) wbase += wave_tot[w];
+  bins[tid] = wbase + x - c;
+  __syncthreads();
+  for (uint32_t base = 0; base < n; base += kOrderBins * kOrderPer) {
+    uint32_t b[kOrderPer];
+    bins_of(base, b);
+#pragma unroll
+    for (int q = 0; q < kOrderPer; ++q) {
+      const uint32_t t = base + uint32_t(q) * kOrderBins + tid;
+      if (t < n) order[atomicAdd(&bins[b[q]], 1u)] = t;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kOrderBins) tile_order_kernel(const uint32_t* __restrict__ counts,
+                                                               uint32_t n,
+                                                               uint32_t* __restrict__ order) {
+  __shared__ uint32_t bins[kOrderBins];
+  __shared__ uint32_t wave_tot[kOrderBins / 64];
+  order_tiles_by_count(counts, n, order, bins, wave_tot);
+}
+
 constexpr int kSingleItems = 8;
 static_assert(kSingleItems == 8, "the vector path loads and stores two uint4 per thread");
 constexpr uint32_t kSingleChunk = uint32_t(kSingleThreads * kSingleItems);
 
+// (order: also the tile order of the counts in `in`, when not null)
 __global__ void __launch_bounds__(kSingleThreads) scan_single_kernel(
     const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ out,
     uint32_t* __restrict__ list, DevStatus* __restrict__ status, unsigned long long capacity,
-    unsigned long long* __restrict__ total_out) {
+    unsigned long long* __restrict__ total_out, uint32_t* __restrict__ order) {
+  static_assert(kSingleThreads == kOrderBins, "the tile order takes the scan's workgroup");
   constexpr int W = kSingleThreads / 64;
   __shared__ uint32_t s_wave[W];
   __shared__ unsigned long long s_wave64[W];
@@ -619,16 +690,24 @@ __global__ void __launch_bounds__(kSingleThreads) scan_single_kernel(
     status->overflow = total > capacity ? 1u : 0u;
   }
   if (threadIdx.x == 0 && total_out != nullptr) *total_out = total;
+  if (order != nullptr) {
+    __shared__ uint32_t s_bins[kOrderBins];
+    __shared__ uint32_t s_tot[kOrderBins / 64];
+    order_tiles_by_count(in, n, order, s_bins, s_tot);
+  }
 }
 
 static hipError_t scan_impl(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
                             uint32_t* list, DevStatus* status, unsigned long long capacity,
-                            hipStream_t st, unsigned long long* total_out) {
+                            hipStream_t st, unsigned long long* total_out,
+                            uint32_t* order = nullptr) {
   if (n <= kSingleScanMax) {
     hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kSingleThreads), 0, st, in, n, out,
-                       list, status, capacity, total_out);
+                       list, status, capacity, total_out, order);
     return hipGetLastError();
   }
+  if (order != nullptr)
+    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderBins), 0, st, in, n, order);
   const uint32_t n_tiles = (n + kScanTile - 1) / kScanTile;
   if (n_tiles > 0)
     hipLaunchKernelGGL(scan_tile_sums_kernel, dim3(n_tiles), dim3(kScanThreads), 0, st, in, n,
@@ -641,10 +720,11 @@ static hipError_t scan_impl(const uint32_t* in, uint32_t n, uint32_t* tile_sums,
   return hipGetLastError();
 }
 
+// order (when not null): the rasters' tile order, longest tiles first.
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
                        DevStatus* status, unsigned long long capacity, hipStream_t st,
-                       unsigned long long* total_out) {
-  return scan_impl(in, n, tile_sums, out, nullptr, status, capacity, st, total_out);
+                       unsigned long long* total_out, uint32_t* order) {
+  return scan_impl(in, n, tile_sums, out, nullptr, status, capacity, st, total_out, order);
 }
 
 // Exclusive scan of a 0/1 flag array and, in the same pass, the compacted

@@ -187,11 +187,12 @@ template <int TW, int TH, int BATCH>
 __global__ void __launch_bounds__(64) raster_fwd_kernel(
     const float* __restrict__ records, const uint32_t* __restrict__ values,
     const uint32_t* __restrict__ ranges, const DevView* __restrict__ views, int n_views,
-    uint32_t n_tiles, uint32_t* __restrict__ work, float* __restrict__ image,
-    float* __restrict__ t_ws, float* __restrict__ t_user, uint32_t* __restrict__ ncontrib) {
+    uint32_t n_tiles, const uint32_t* __restrict__ order, uint32_t* __restrict__ work,
+    float* __restrict__ image, float* __restrict__ t_ws, float* __restrict__ t_user,
+    uint32_t* __restrict__ ncontrib) {
   __shared__ float4 s0[BATCH], s1[BATCH], s2[BATCH];
-  for (uint32_t tile = next_tile(work, true); tile < n_tiles; tile = next_tile(work, false))
-    raster_fwd_tile<TW, TH, BATCH>(tile, s0, s1, s2, records, values, ranges, views, n_views,
+  for (uint32_t q = next_tile(work, true); q < n_tiles; q = next_tile(work, false))
+    raster_fwd_tile<TW, TH, BATCH>(order[q], s0, s1, s2, records, values, ranges, views, n_views,
                                    image, t_ws, t_user, ncontrib);
 }
 
@@ -447,14 +448,16 @@ template <int TW, int TH, int BATCH>
 __global__ void __launch_bounds__(64) raster_bwd_kernel(
     const float* __restrict__ records, const uint32_t* __restrict__ values,
     const uint32_t* __restrict__ ranges, const DevView* __restrict__ views, int n_views,
-    uint32_t n_tiles, uint32_t* __restrict__ work, uint32_t* __restrict__ grad_dirty,
+    uint32_t n_tiles, const uint32_t* __restrict__ order, uint32_t* __restrict__ work,
+    uint32_t* __restrict__ grad_dirty,
     const float* __restrict__ t_ws,
     const uint32_t* __restrict__ ncontrib, const float* __restrict__ d_image,
     const float* __restrict__ d_tfinal, const float* __restrict__ l1_image,
     const float* __restrict__ l1_target, float l1_scale, float* __restrict__ grad2d) {
   __shared__ float4 s0[BATCH], s1[BATCH], s2[BATCH];
   if (blockIdx.x == 0 && threadIdx.x == 0) *grad_dirty = 1u;
-  for (uint32_t tile = next_tile(work, true); tile < n_tiles; tile = next_tile(work, false)) {
+  for (uint32_t q = next_tile(work, true); q < n_tiles; q = next_tile(work, false)) {
+    const uint32_t tile = order[q];
     if (d_tfinal)
       raster_bwd_tile<TW, TH, BATCH, true>(tile, s0, s1, s2, records, values, ranges, views,
                                            n_views, t_ws, ncontrib, d_image, d_tfinal, l1_image,
@@ -471,16 +474,19 @@ __global__ void reset_counter_kernel(uint32_t* __restrict__ c) {
 }
 
 // Launch geometry: one wavefront per tile (grid = tiles), or a persistent
-// grid of `persistent_blocks` wavefronts taking tiles from a queue.
+// grid of `persistent_blocks` wavefronts taking tiles from a queue; either
+// way the q-th tile handed out is order[q] (the binning's order, longest
+// tiles first).
 struct RasterLaunch {
   uint32_t n_tiles;
   uint32_t* work;            // queue counter, or nullptr
   uint32_t grid;
+  const uint32_t* order;
 };
 
 static RasterLaunch raster_geometry(uint32_t n_tiles, uint32_t* work, uint32_t persistent_blocks,
-                                    hipStream_t st) {
-  RasterLaunch g{n_tiles, nullptr, n_tiles};
+                                    const uint32_t* order, hipStream_t st) {
+  RasterLaunch g{n_tiles, nullptr, n_tiles, order};
   if (work && persistent_blocks > 0 && persistent_blocks < n_tiles) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, work);
     g.work = work;
@@ -495,8 +501,8 @@ static hipError_t raster_fwd_t(const RasterLaunch& g, const float* records, cons
                                float* image, float* t_ws, float* t_user, uint32_t* ncontrib,
                                hipStream_t st) {
   hipLaunchKernelGGL((raster_fwd_kernel<TW, TH, BATCH>), dim3(g.grid), dim3(64), 0, st, records,
-                     values, ranges, views, n_views, g.n_tiles, g.work, image, t_ws, t_user,
-                     ncontrib);
+                     values, ranges, views, n_views, g.n_tiles, g.order, g.work, image, t_ws,
+                     t_user, ncontrib);
   return hipGetLastError();
 }
 
@@ -509,8 +515,8 @@ static hipError_t raster_bwd_t(const RasterLaunch& g, uint32_t* grad_dirty, cons
                                const float* l1_target, float l1_scale, float* grad2d,
                                hipStream_t st) {
   hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, BATCH>), dim3(g.grid), dim3(64), 0, st, records,
-                     values, ranges, views, n_views, g.n_tiles, g.work, grad_dirty, t_ws, ncontrib,
-                     d_image, d_tfinal, l1_image, l1_target, l1_scale, grad2d);
+                     values, ranges, views, n_views, g.n_tiles, g.order, g.work, grad_dirty, t_ws,
+                     ncontrib, d_image, d_tfinal, l1_image, l1_target, l1_scale, grad2d);
   return hipGetLastError();
 }
 
@@ -542,11 +548,12 @@ static hipError_t raster_bwd_t(const RasterLaunch& g, uint32_t* grad_dirty, cons
 
 hipError_t launch_raster_fwd(int tw, int th, int batch, uint32_t persistent_blocks,
                              uint32_t* work, const float* records, const uint32_t* values,
-                             const uint32_t* ranges, const DevView* views, int n_views,
+                             const uint32_t* ranges, const uint32_t* order,
+                             const DevView* views, int n_views,
                              uint32_t n_tiles, float* image, float* t_ws, float* t_user,
                              uint32_t* ncontrib, hipStream_t st) {
   if (n_tiles == 0) return hipSuccess;
-  const RasterLaunch g = raster_geometry(n_tiles, work, persistent_blocks, st);
+  const RasterLaunch g = raster_geometry(n_tiles, work, persistent_blocks, order, st);
   UBS_TILE_DISPATCH(raster_fwd_t, g, records, values, ranges, views, n_views, image, t_ws, t_user,
                     ncontrib, st);
 }
@@ -554,13 +561,14 @@ hipError_t launch_raster_fwd(int tw, int th, int batch, uint32_t persistent_bloc
 hipError_t launch_raster_bwd(int tw, int th, int batch, uint32_t persistent_blocks,
                              uint32_t* work, uint32_t* grad_dirty, const float* records,
                              const uint32_t* values,
-                             const uint32_t* ranges, const DevView* views, int n_views,
+                             const uint32_t* ranges, const uint32_t* order,
+                             const DevView* views, int n_views,
                              uint32_t n_tiles, const float* t_ws, const uint32_t* ncontrib,
                              const float* d_image, const float* d_tfinal, const float* l1_image,
                              const float* l1_target, float l1_scale, float* grad2d,
                              hipStream_t st) {
   if (n_tiles == 0) return hipSuccess;
-  const RasterLaunch g = raster_geometry(n_tiles, work, persistent_blocks, st);
+  const RasterLaunch g = raster_geometry(n_tiles, work, persistent_blocks, order, st);
   UBS_TILE_DISPATCH(raster_bwd_t, g, grad_dirty, records, values, ranges, views, n_views, t_ws,
                     ncontrib, d_image, d_tfinal, l1_image, l1_target, l1_scale, grad2d, st);
 }
