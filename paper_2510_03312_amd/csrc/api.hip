@@ -35,7 +35,7 @@ hipError_t launch_tile_sort(unsigned long long* comp, const unsigned long long* 
                             const uint32_t* tile_cursor, const DevStatus* status,
                             unsigned long long* keys_out, uint32_t* vals_out, uint32_t* ranges,
                             uint32_t n_tiles, int digit_bits, int rec_bits, uint32_t* big_tiles,
-                            uint32_t* n_big_tiles, hipStream_t st);
+                            uint32_t* n_big_tiles, const uint32_t* order, hipStream_t st);
 hipError_t launch_raster_fwd(int tw, int th, int batch, uint32_t persistent_blocks,
                              uint32_t* work, const float* records, const uint32_t* values,
                              const uint32_t* ranges, const uint32_t* order,
@@ -434,7 +434,7 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
                            at<unsigned long long>(ws, L.pub.off_keys),
                            at<uint32_t>(ws, L.pub.off_values), at<uint32_t>(ws, L.pub.off_ranges),
                            n_tiles, L.digit_bits, L.rec_bits, at<uint32_t>(ws, L.off_big_tiles),
-                           n_big_tiles, s));
+                           n_big_tiles, at<uint32_t>(ws, L.off_tile_order), s));
   stage_mark(frame, UBS_STAGE_SORT, 1, s);
   return UBS_OK;
 }

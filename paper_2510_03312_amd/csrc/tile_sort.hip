@@ -141,14 +141,15 @@ __global__ void __launch_bounds__(64) tile_sort_small_kernel(
     uint32_t slot_cap, const uint32_t* __restrict__ tile_counts,
     const uint32_t* __restrict__ tile_cursor, const DevStatus* __restrict__ status,
     unsigned long long* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-    uint32_t* __restrict__ ranges, uint32_t n_tiles, uint32_t* __restrict__ big_tiles,
-    uint32_t* __restrict__ n_big_tiles) {
+    uint32_t* __restrict__ ranges, uint32_t n_tiles, const uint32_t* __restrict__ order,
+    uint32_t* __restrict__ big_tiles, uint32_t* __restrict__ n_big_tiles) {
   __shared__ unsigned long long s_keys[kSmallSort];
   constexpr int Q = int(kSmallSort / 64);
   const uint32_t lane = threadIdx.x;
   const bool overflow = status->overflow != 0u;
   const bool spill = status->spill != 0u;
-  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+  for (uint32_t q = blockIdx.x; q < n_tiles; q += gridDim.x) {
+    const uint32_t t = order[q];   // (longest tiles first)
     const uint32_t n = overflow ? 0u : tile_counts[t];
     // the cursor is the segment start, or its end once the spill pass ran
     const uint32_t start = n ? (spill ? tile_cursor[t] - n : tile_cursor[t]) : 0u;
@@ -246,19 +247,20 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_sort_kernel(
   }
 }
 
-// big_tiles: n_tiles words; n_big_tiles must be zero.
+// big_tiles: n_tiles words; n_big_tiles must be zero; order: the tiles
+// longest first (the scan's order).
 hipError_t launch_tile_sort(unsigned long long* comp, const unsigned long long* slots,
                             uint32_t slot_cap, const uint32_t* tile_counts,
                             const uint32_t* tile_cursor,
                             const DevStatus* status, unsigned long long* keys_out,
                             uint32_t* vals_out, uint32_t* ranges, uint32_t n_tiles,
                             int digit_bits, int rec_bits, uint32_t* big_tiles,
-                            uint32_t* n_big_tiles, hipStream_t st) {
+                            uint32_t* n_big_tiles, const uint32_t* order, hipStream_t st) {
   if (n_tiles == 0) return hipSuccess;
   const uint32_t grid = n_tiles < 65536u ? n_tiles : 65536u;
   hipLaunchKernelGGL(tile_sort_small_kernel, dim3(grid), dim3(64), 0, st, comp, slots,
                      slot_cap, tile_counts, tile_cursor, status, keys_out, vals_out, ranges,
-                     n_tiles, big_tiles, n_big_tiles);
+                     n_tiles, order, big_tiles, n_big_tiles);
   // up to four workgroups per CU (the LDS sort takes 37 KiB of the 160)
   const uint32_t big_grid = n_tiles < 1024u ? n_tiles : 1024u;
   hipLaunchKernelGGL(tile_sort_kernel, dim3(big_grid), dim3(kTileSortThreads), 0, st, comp,
