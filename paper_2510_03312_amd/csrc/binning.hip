@@ -563,12 +563,15 @@ __device__ __forceinline__ void order_tiles_by_count(const uint32_t* __restrict_
   };
   bins[tid] = 0u;
   __syncthreads();
+  // up to kOrderBins * kOrderPer tiles: one round, each tile's rank in its
+  // bin kept from the counting atomic; beyond that a second pass
+  const bool one_round = n <= uint32_t(kOrderBins * kOrderPer);
+  uint32_t b0[kOrderPer], rank[kOrderPer];
   for (uint32_t base = 0; base < n; base += kOrderBins * kOrderPer) {
-    uint32_t b[kOrderPer];
-    bins_of(base, b);
+    bins_of(base, b0);
 #pragma unroll
     for (int q = 0; q < kOrderPer; ++q)
-      if (base + uint32_t(q) * kOrderBins + tid < n) atomicAdd(&bins[b[q]], 1u);
+      rank[q] = base + uint32_t(q) * kOrderBins + tid < n ? atomicAdd(&bins[b0[q]], 1u) : 0u;
   }
   __syncthreads();
   // exclusive scan of the bins: within wavefronts, then over their totals
@@ -586,6 +589,14 @@ __device__ __forceinline__ void order_tiles_by_count(const uint32_t* __restrict_
   for (int w = 0; w < wave; ++w) wbase += wave_tot[w];
   bins[tid] = wbase + x - c;
   __syncthreads();
+  if (one_round) {
+#pragma unroll
+    for (int q = 0; q < kOrderPer; ++q) {
+      const uint32_t t = uint32_t(q) * kOrderBins + tid;
+      if (t < n) order[bins[b0[q]] + rank[q]] = t;
+    }
+    return;
+  }
   for (uint32_t base = 0; base < n; base += kOrderBins * kOrderPer) {
     uint32_t b[kOrderPer];
     bins_of(base, b);
