@@ -402,8 +402,8 @@ __device__ __forceinline__ void raster_bwd_tile(
       gv[9] = a_b;
       // sums over the wavefront: halves folded onto each other (permlane32
       // swap: field 2p in lanes 0-31, 2p+1 in lanes 32-63), row pairs folded
-      // (permlane16 swap: one field per row), DPP sums within the rows;
-      // every lane of a row ends with the totals of its row's fields
+      // (permlane16 swap: one field per row), then DPP sums within rows and
+      // half-rows
       float h[5];
 #pragma unroll
       for (int p = 0; p < 5; ++p) {
@@ -419,18 +419,26 @@ __device__ __forceinline__ void raster_bwd_tile(
         t3[1] = s1.a + s1.b;
         t3[2] = s2.a + s2.b;
       }
-      row_sum_all<3>(t3);
-      // keep the last DPP add ahead of the branch (sunk into it, the add
+      // t3[0] and t3[1] share one register from here: pairs of lanes 8
+      // apart are summed in each, half-rows take t3[0]'s (lanes 0-7) or
+      // t3[1]'s (8-15) sums, and a half-row mirror and two quad
+      // permutations finish the 8-lane sums; t3[2] is summed over its rows
+      float x0 = t3[0] + dpp_row<0x128>(t3[0]), x1 = t3[1] + dpp_row<0x128>(t3[1]);
+      asm volatile("" : "+v"(x0), "+v"(x1));   // (both sums, then a select, not a branch)
+      float u = (lane & 8) ? x1 : x0;
+      u += dpp_row<0x141>(u);   // lane l of a half-row and lane 7 - l
+      u += dpp_row<0x4E>(u);    // quad permutation [2, 3, 0, 1]
+      u += dpp_row<0xB1>(u);    // quad permutation [1, 0, 3, 2]
+      row_sum_all<1>(&t3[2]);
+      // keep the last DPP adds ahead of the branch (sunk into it, an add
       // could no longer take its operand through DPP)
-#pragma unroll
-      for (int q = 0; q < 3; ++q) asm volatile("" : "+v"(t3[q]));
-      if ((lane & 15) == 15) {
+      asm volatile("" : "+v"(u), "+v"(t3[2]));
+      if ((lane & 7) == 7) {
         const int row = lane >> 4;
         const int sub = row == 1 ? 2 : (row == 2 ? 1 : row);
         float* g = grad2d + size_t(__float_as_uint(g2.w)) * kGradFloats;
-        atomicAdd(g + sub, t3[0]);
-        atomicAdd(g + 4 + sub, t3[1]);
-        if ((row & 1) == 0) atomicAdd(g + 8 + (row >> 1), t3[2]);
+        atomicAdd(g + ((lane & 8) ? 4 : 0) + sub, u);
+        if ((lane & 15) == 15 && (row & 1) == 0) atomicAdd(g + 8 + (row >> 1), t3[2]);
       }
     };
     if (hi <= stop_min) {
