@@ -13,8 +13,8 @@
 // the transmittance in front of a record is recovered by division.  A lane
 // first sums the gradient terms of its own pixels; the wavefront then folds
 // its ten per-record sums onto fewer lanes with lane swaps, finishes them
-// with DPP sums within 16-lane rows, and four lanes add the ten totals to
-// the record's accumulator with one atomic each.
+// with DPP sums within 16-lane rows and half-rows, and ten lanes add the
+// ten totals to the record's accumulator in one atomic instruction.
 //
 // Both passes take every per-pixel decision (support test, skip, stop)
 // through the same inline functions, so the backward pass visits exactly
@@ -433,12 +433,14 @@ __device__ __forceinline__ void raster_bwd_tile(
       // keep the last DPP adds ahead of the branch (sunk into it, an add
       // could no longer take its operand through DPP)
       asm volatile("" : "+v"(u), "+v"(t3[2]));
-      if ((lane & 7) == 7) {
+      // one atomic instruction: lanes 7 + 8k add the eight totals of u, lanes
+      // 6 and 38 (rows 0 and 2 of t3[2]) fields 8 and 9
+      const bool lane_u = (lane & 7) == 7, lane_t = (lane & 31) == 6;
+      if (lane_u || lane_t) {
         const int row = lane >> 4;
         const int sub = row == 1 ? 2 : (row == 2 ? 1 : row);
-        float* g = grad2d + size_t(__float_as_uint(g2.w)) * kGradFloats;
-        atomicAdd(g + ((lane & 8) ? 4 : 0) + sub, u);
-        if ((lane & 15) == 15 && (row & 1) == 0) atomicAdd(g + 8 + (row >> 1), t3[2]);
+        const int field = lane_u ? ((lane & 8) ? 4 : 0) + sub : 8 + (row >> 1);
+        atomicAdd(grad2d + size_t(__float_as_uint(g2.w)) * kGradFloats + field, lane_u ? u : t3[2]);
       }
     };
     if (hi <= stop_min) {
