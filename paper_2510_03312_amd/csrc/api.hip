@@ -24,7 +24,8 @@ hipError_t launch_bin_count(const float* records, const DevView* views, int n_vi
                             uint32_t slot_cap, DevStatus* status, float* grad2d, hipStream_t st);
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
                        DevStatus* status, unsigned long long capacity, hipStream_t st,
-                       unsigned long long* total_out, uint32_t* order);
+                       unsigned long long* total_out, uint32_t* order, uint32_t* order_hist);
+uint64_t order_hist_words(uint64_t n_tiles);
 hipError_t launch_bin_emit(const float* records, const DevView* views, int n_views,
                            uint32_t n_records, const uint32_t* hit_mask, const uint32_t* big_list,
                            const uint32_t* big_count, uint32_t* tile_cursor,
@@ -257,6 +258,7 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.off_tile_counts = take(4 * (n_tiles + 2));
   l.off_big_tiles = take(4 * n_tiles);
   l.off_tile_order = take(4 * n_tiles);
+  l.off_order_hist = take(4 * order_hist_words(n_tiles));
   l.off_tile_cursor = take(4 * n_tiles);
   l.off_hit_mask = take(4 * n_rec);
   l.off_big_list = take(4 * n_rec);
@@ -423,7 +425,7 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
   stage_mark(frame, UBS_STAGE_SCAN, 0, s);
   // segment starts of the tiles; the total sets pairs_needed and overflow
   UBS_HIP(launch_scan(tile_counts, n_tiles, sums, tile_cursor, status, cap, s, nullptr,
-                      at<uint32_t>(ws, L.off_tile_order)));
+                      at<uint32_t>(ws, L.off_tile_order), at<uint32_t>(ws, L.off_order_hist)));
   stage_mark(frame, UBS_STAGE_SCAN, 1, s);
   stage_mark(frame, UBS_STAGE_BIN_EMIT, 0, s);
   UBS_HIP(launch_bin_emit(records, views, frame->n_views, n_rec, hit_mask, big_list, big_count,

@@ -540,38 +540,36 @@ constexpr int kSingleThreads = 1024;
 // Order in which the rasters take the tiles: by pair count, largest first
 // (ties in no particular order), so that the last tiles a launch hands out
 // are small ones and the SIMDs finish together.  A counting sort of the
-// tiles on min(count, kOrderBins - 1) by one workgroup of kOrderBins threads.
+// tiles on min(count, kOrderBins - 1), here by one workgroup of kOrderBins
+// threads for up to kOrderBins * kOrderPer tiles (each tile's rank in its
+// bin kept from its counting atomic).
 constexpr int kOrderBins = 1024;
-constexpr int kOrderPer = 8;   // tiles per thread per round (their loads issued together)
+constexpr int kOrderPer = 8;
+
+__device__ __forceinline__ uint32_t order_bin(uint32_t count) {
+  // ascending bins put the longest tiles first
+  return uint32_t(kOrderBins - 1) - min(count, uint32_t(kOrderBins - 1));
+}
 
 __device__ __forceinline__ void order_tiles_by_count(const uint32_t* __restrict__ counts,
                                                      uint32_t n, uint32_t* __restrict__ order,
                                                      uint32_t* bins, uint32_t* wave_tot) {
   const uint32_t tid = threadIdx.x;
-  // bin kOrderBins - 1 - min(count, kOrderBins - 1): an ascending scan of
-  // the bins puts the longest tiles first
-  auto bins_of = [&](uint32_t base, uint32_t* b) {
+  uint32_t b[kOrderPer], rank[kOrderPer];
+  bins[tid] = 0u;
+  __syncthreads();
+  {
     uint32_t c[kOrderPer];
 #pragma unroll
     for (int q = 0; q < kOrderPer; ++q) {
-      const uint32_t t = base + uint32_t(q) * kOrderBins + tid;
+      const uint32_t t = uint32_t(q) * kOrderBins + tid;
       c[q] = t < n ? counts[t] : 0u;
     }
 #pragma unroll
-    for (int q = 0; q < kOrderPer; ++q)
-      b[q] = uint32_t(kOrderBins - 1) - min(c[q], uint32_t(kOrderBins - 1));
-  };
-  bins[tid] = 0u;
-  __syncthreads();
-  // up to kOrderBins * kOrderPer tiles: one round, each tile's rank in its
-  // bin kept from the counting atomic; beyond that a second pass
-  const bool one_round = n <= uint32_t(kOrderBins * kOrderPer);
-  uint32_t b0[kOrderPer], rank[kOrderPer];
-  for (uint32_t base = 0; base < n; base += kOrderBins * kOrderPer) {
-    bins_of(base, b0);
-#pragma unroll
-    for (int q = 0; q < kOrderPer; ++q)
-      rank[q] = base + uint32_t(q) * kOrderBins + tid < n ? atomicAdd(&bins[b0[q]], 1u) : 0u;
+    for (int q = 0; q < kOrderPer; ++q) {
+      b[q] = order_bin(c[q]);
+      rank[q] = uint32_t(q) * kOrderBins + tid < n ? atomicAdd(&bins[b[q]], 1u) : 0u;
+    }
   }
   __syncthreads();
   // exclusive scan of the bins: within wavefronts, then over their totals
@@ -589,31 +587,92 @@ __device__ __forceinline__ void order_tiles_by_count(const uint32_t* __restrict_
   for (int w = 0; w < wave; ++w) wbase += wave_tot[w];
   bins[tid] = wbase + x - c;
   __syncthreads();
-  if (one_round) {
 #pragma unroll
-    for (int q = 0; q < kOrderPer; ++q) {
-      const uint32_t t = uint32_t(q) * kOrderBins + tid;
-      if (t < n) order[bins[b0[q]] + rank[q]] = t;
-    }
-    return;
+  for (int q = 0; q < kOrderPer; ++q) {
+    const uint32_t t = uint32_t(q) * kOrderBins + tid;
+    if (t < n) order[bins[b[q]] + rank[q]] = t;
   }
-  for (uint32_t base = 0; base < n; base += kOrderBins * kOrderPer) {
-    uint32_t b[kOrderPer];
-    bins_of(base, b);
+}
+
+constexpr uint32_t kOrderOneRound = uint32_t(kOrderBins * kOrderPer);
+
+// Frames of more than kOrderOneRound tiles: the same counting sort by
+// workgroups of kOrderGroupTiles tiles (bin counts per workgroup, one
+// workgroup turning them into each workgroup's offsets bin by bin, then the
+// scatter), so that no one workgroup walks every tile.
+constexpr uint32_t kOrderGroupTiles = 2048;   // 256 threads x 8
+
+__global__ void __launch_bounds__(256) tile_order_hist_kernel(const uint32_t* __restrict__ counts,
+                                                              uint32_t n,
+                                                              uint32_t* __restrict__ hist) {
+  __shared__ uint32_t bins[kOrderBins];
+  for (int i = int(threadIdx.x); i < kOrderBins; i += 256) bins[i] = 0u;
+  __syncthreads();
+  const uint32_t t0 = blockIdx.x * kOrderGroupTiles + threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < kOrderPer; ++q) {
-      const uint32_t t = base + uint32_t(q) * kOrderBins + tid;
-      if (t < n) order[atomicAdd(&bins[b[q]], 1u)] = t;
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t t = t0 + uint32_t(q) * 256u;
+    if (t < n) atomicAdd(&bins[order_bin(counts[t])], 1u);
+  }
+  __syncthreads();
+  for (int i = int(threadIdx.x); i < kOrderBins; i += 256)
+    hist[size_t(blockIdx.x) * kOrderBins + i] = bins[i];
+}
+
+// hist[g][b] becomes the position of workgroup g's first tile of bin b:
+// bins in ascending order, workgroups in order within a bin.
+__global__ void __launch_bounds__(kOrderBins) tile_order_offsets_kernel(uint32_t* __restrict__ hist,
+                                                                        uint32_t groups) {
+  __shared__ uint32_t wave_tot[kOrderBins / 64];
+  const uint32_t b = threadIdx.x;
+  uint32_t c = 0;
+  // (eight workgroups' counts loaded at a time)
+  for (uint32_t g0 = 0; g0 < groups; g0 += 8) {
+    uint32_t h[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      h[q] = g0 + q < groups ? hist[size_t(g0 + q) * kOrderBins + b] : 0u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c += h[q];
+  }
+  const int lane = int(b & 63), wave = int(b >> 6);
+  uint32_t x = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wave_tot[wave] = x;
+  __syncthreads();
+  uint32_t run = x - c;
+  for (int w = 0; w < wave; ++w) run += wave_tot[w];
+  for (uint32_t g0 = 0; g0 < groups; g0 += 8) {
+    uint32_t h[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      h[q] = g0 + q < groups ? hist[size_t(g0 + q) * kOrderBins + b] : 0u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (g0 + q < groups) hist[size_t(g0 + q) * kOrderBins + b] = run;
+      run += h[q];
     }
   }
 }
 
-__global__ void __launch_bounds__(kOrderBins) tile_order_kernel(const uint32_t* __restrict__ counts,
-                                                               uint32_t n,
-                                                               uint32_t* __restrict__ order) {
+__global__ void __launch_bounds__(256) tile_order_scatter_kernel(const uint32_t* __restrict__ counts,
+                                                                 uint32_t n,
+                                                                 const uint32_t* __restrict__ hist,
+                                                                 uint32_t* __restrict__ order) {
   __shared__ uint32_t bins[kOrderBins];
-  __shared__ uint32_t wave_tot[kOrderBins / 64];
-  order_tiles_by_count(counts, n, order, bins, wave_tot);
+  for (int i = int(threadIdx.x); i < kOrderBins; i += 256)
+    bins[i] = hist[size_t(blockIdx.x) * kOrderBins + i];
+  __syncthreads();
+  const uint32_t t0 = blockIdx.x * kOrderGroupTiles + threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t t = t0 + uint32_t(q) * 256u;
+    if (t < n) order[atomicAdd(&bins[order_bin(counts[t])], 1u)] = t;
+  }
 }
 
 constexpr int kSingleItems = 8;
@@ -711,14 +770,23 @@ __global__ void __launch_bounds__(kSingleThreads) scan_single_kernel(
 static hipError_t scan_impl(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
                             uint32_t* list, DevStatus* status, unsigned long long capacity,
                             hipStream_t st, unsigned long long* total_out,
-                            uint32_t* order = nullptr) {
+                            uint32_t* order = nullptr, uint32_t* order_hist = nullptr) {
+  // the tile order: by the scan's own workgroup up to kOrderOneRound tiles,
+  // else by its kernels
+  if (order != nullptr && n > kOrderOneRound) {
+    const uint32_t groups = (n + kOrderGroupTiles - 1) / kOrderGroupTiles;
+    hipLaunchKernelGGL(tile_order_hist_kernel, dim3(groups), dim3(256), 0, st, in, n, order_hist);
+    hipLaunchKernelGGL(tile_order_offsets_kernel, dim3(1), dim3(kOrderBins), 0, st, order_hist,
+                       groups);
+    hipLaunchKernelGGL(tile_order_scatter_kernel, dim3(groups), dim3(256), 0, st, in, n,
+                       order_hist, order);
+    order = nullptr;
+  }
   if (n <= kSingleScanMax) {
     hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kSingleThreads), 0, st, in, n, out,
                        list, status, capacity, total_out, order);
     return hipGetLastError();
   }
-  if (order != nullptr)
-    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderBins), 0, st, in, n, order);
   const uint32_t n_tiles = (n + kScanTile - 1) / kScanTile;
   if (n_tiles > 0)
     hipLaunchKernelGGL(scan_tile_sums_kernel, dim3(n_tiles), dim3(kScanThreads), 0, st, in, n,
@@ -731,11 +799,17 @@ static hipError_t scan_impl(const uint32_t* in, uint32_t n, uint32_t* tile_sums,
   return hipGetLastError();
 }
 
-// order (when not null): the rasters' tile order, longest tiles first.
+// order (when not null): the rasters' tile order, longest tiles first;
+// order_hist: order_hist_words(n) words for it.
 hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint32_t* out,
                        DevStatus* status, unsigned long long capacity, hipStream_t st,
-                       unsigned long long* total_out, uint32_t* order) {
-  return scan_impl(in, n, tile_sums, out, nullptr, status, capacity, st, total_out, order);
+                       unsigned long long* total_out, uint32_t* order, uint32_t* order_hist) {
+  return scan_impl(in, n, tile_sums, out, nullptr, status, capacity, st, total_out, order,
+                   order_hist);
+}
+
+uint64_t order_hist_words(uint64_t n_tiles) {
+  return uint64_t(kOrderBins) * ((n_tiles + kOrderGroupTiles - 1) / kOrderGroupTiles);
 }
 
 // Exclusive scan of a 0/1 flag array and, in the same pass, the compacted

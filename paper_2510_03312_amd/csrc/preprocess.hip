@@ -131,10 +131,10 @@ __device__ __forceinline__ void record_gradient_from_sums(const float* __restric
   g[6] = g[6] * 0.69314718f;
 }
 
-// Thread t runs the adjoint of the primitive at entry t of the kept lists
-// (list t / cap) and writes its gradient to column t of the compacted
-// [F][kKeptLists cap] buffer (coalesced); scatter_dparams_kernel moves it to
-// the primitive's column.
+// One thread per entry of the kept lists: the adjoint of the primitive at
+// entry e of list l, its gradient written to column t = l cap + e of the
+// compacted [F][kKeptLists cap] buffer (coalesced); scatter_dparams_kernel
+// moves it to the primitive's column.
 template <typename T, int C, int ROT>
 __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int scene,
                                                              const DevView* __restrict__ views,
@@ -143,10 +143,13 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int sce
                                                              float* __restrict__ grad2d,
                                                              LiveIn kept,
                                                              float* __restrict__ compact) {
-  // thread t takes entry t % cap of kept list t / cap (cap is a multiple of
-  // the workgroup size, so a workgroup stays inside one list)
-  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
-  const uint32_t lo = t / kept.cap, pos = t - lo * kept.cap;
+  // workgroup b takes entries 256 (b / kKeptLists) + [0, 256) of kept list
+  // b mod kKeptLists (cap is a multiple of 256), so the workgroups holding
+  // entries come first in the grid whatever the lists' counts; thread t =
+  // list cap + entry writes compacted column t
+  const uint32_t lo = blockIdx.x % kKeptLists;
+  const uint32_t pos = (blockIdx.x / kKeptLists) * 256u + threadIdx.x;
+  const uint32_t t = lo * kept.cap + pos;
   if (pos >= kept.count[lo]) return;
   const int64_t i = kept.list[t];
   Raw<C, ROT> r;

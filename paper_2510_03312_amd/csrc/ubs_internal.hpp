@@ -159,6 +159,7 @@ struct Layout {
   uint64_t off_keys0, off_values0;   // sorted keys and values
   uint64_t off_tfinal_ws;            // final transmittance kept for the adjoint
   uint64_t off_tile_order;   // the rasters' tile order (longest first)
+  uint64_t off_order_hist;   // its per-workgroup bin counts (large frames)
   uint64_t off_live, off_live_list, off_live_count;  // per-primitive live flags, compacted list, counts
   uint64_t off_grad_compact;         // adjoint output of live primitives, [F][n] per scene
   uint64_t off_pre_partials;         // per-workgroup preprocess counts [2][n_pre_partials]
