@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define UBS_ABI_VERSION 1
+#define UBS_ABI_VERSION 2
 #define UBS_MAX_QUERY_DIMS 7  /* C <= 7: N <= 10 (C = 1, 2 unsupported) */
 #define UBS_MAX_VIEWS 4096
 #define UBS_MAX_SCENES 256
@@ -199,8 +199,9 @@ typedef struct {
  *             conic = inverse of the 2-D covariance, r(p) = a dx^2 +
  *             2 b dx dy + c dy^2 (dx = p_x - mean x); the record touches
  *             pixels with r <= rho, where rho is the largest r with
- *             o(q) (1 - r)^beta_x >= 1/255.  A record with !(rho > 0) is
- *             culled.
+ *             o(q) (1 - r)^beta_x >= 1/255.  Only the records that
+ *             survived culling (live[] = 1) are written; the fields of a
+ *             culled record are left as they were.
  *   keys      uint64 [pair_capacity] sorted keys: (global tile << 32) |
  *             float32 bits of depth; global tile = tile_base[v] + ty *
  *             tiles_x(v) + tx with tile_base[v] the tile count of views
@@ -211,8 +212,12 @@ typedef struct {
  *   ncontrib  uint32 [n_pixels] per pixel: one past the position (within
  *             its tile's range) of its last contributor.
  *   grad2d    float32 [n_records][10] d loss / d record fields 0-4, 6-10,
- *             after ubs_render_bwd (rows of culled records, rho <= 0, are
- *             not written).
+ *             after ubs_render_bwd (rows of culled records are not
+ *             written).
+ *   live      uint8 [n_records] 1 for a record that survived culling
+ *             (then rho > 0), 0 for a culled one; written by
+ *             ubs_preprocess for every record, read by the binning and
+ *             the adjoint.
  * Other regions are private scratch.
  */
 typedef struct {
@@ -225,6 +230,7 @@ typedef struct {
   int32_t n_views;
   uint64_t off_status, off_records, off_keys, off_values, off_ranges;
   uint64_t off_ncontrib, off_grad2d;
+  uint64_t off_live;
 } ubs_layout;
 
 /* Status block at ws + off_status (device memory, uint32/uint64 fields). */
@@ -250,10 +256,10 @@ typedef struct {
  * ws == NULL: size query.  Validates the frame and fills *layout (which
  * must then be non-NULL); enqueues nothing.
  * ws != NULL: ws must hold at least layout.bytes (ws_bytes); writes the
- * records of every (view, primitive), clears the status block and the
- * private tables.  Culled records (behind the near plane z <= 0.2,
- * non-positive-definite 2-D covariance, o(q) < 1/255, non-finite
- * parameters) get rho = 0.
+ * live flag of every (view, primitive) record and the fields of the live
+ * ones, clears the status block and the private tables.  Culled records
+ * (behind the near plane z <= 0.2, non-positive-definite 2-D covariance,
+ * o(q) < 1/255, non-finite parameters) get live = 0 and no fields.
  */
 ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
                           ubs_layout* layout, void* stream);
@@ -264,9 +270,9 @@ ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
  * (Section 4.5: splats binned to screen tiles and depth-ordered per tile),
  * with a splat's extent given by its Mahalanobis distance r (Section 3,
  * equation r) and its support r <= rho (Beta kernel, Section 3 / 4.3).
- * Reads the records in ws (written by ubs_preprocess, or by the caller in
- * the documented record format after a ubs_preprocess call on the same
- * frame).  A record overlaps a tile iff the minimum of r over the rectangle
+ * Reads the live records in ws (written by ubs_preprocess, or by the caller
+ * in the documented record format, with their live flags, after a
+ * ubs_preprocess call on the same frame).  A record overlaps a tile iff the minimum of r over the rectangle
  * spanned by the tile's pixel centres (clipped to the image) is at most
  * rho (1 + 2^-10), evaluated in float64 without contraction.  Keys are
  * sorted ascending; equal keys keep record-index order (the result is that

@@ -67,7 +67,8 @@ class UbsLayout(ctypes.Structure):
                 ("n_pixels", c_int64), ("pair_capacity", c_int64), ("key_bits", c_int32),
                 ("n_views", c_int32), ("off_status", c_uint64), ("off_records", c_uint64),
                 ("off_keys", c_uint64), ("off_values", c_uint64), ("off_ranges", c_uint64),
-                ("off_ncontrib", c_uint64), ("off_grad2d", c_uint64)]
+                ("off_ncontrib", c_uint64), ("off_grad2d", c_uint64),
+                ("off_live", c_uint64)]
 
 
 class UbsStatusBlock(ctypes.Structure):

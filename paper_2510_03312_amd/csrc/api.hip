@@ -18,7 +18,8 @@ hipError_t launch_bin_prepare(uint32_t* words, size_t n_words, const uint32_t* p
 hipError_t launch_preprocess_bwd(bool fp64, const DevScene& S, int scene, const DevView* views,
                                  int n_views, const float* records, float* grad2d, LiveIn kept,
                                  float* compact, hipStream_t st);
-hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
+hipError_t launch_bin_count(const float* records, const uint8_t* live, const DevView* views,
+                            int n_views,
                             uint32_t n_records, uint32_t* tile_counts, uint32_t* hit_mask,
                             uint32_t* big_list, uint32_t* big_count, unsigned long long* slots,
                             uint32_t slot_cap, DevStatus* status, float* grad2d, hipStream_t st);
@@ -26,7 +27,8 @@ hipError_t launch_scan(const uint32_t* in, uint32_t n, uint32_t* tile_sums, uint
                        DevStatus* status, unsigned long long capacity, hipStream_t st,
                        unsigned long long* total_out, uint32_t* order, uint32_t* order_hist);
 uint64_t order_hist_words(uint64_t n_tiles);
-hipError_t launch_bin_emit(const float* records, const DevView* views, int n_views,
+hipError_t launch_bin_emit(const float* records, const uint8_t* live, const DevView* views,
+                           int n_views,
                            uint32_t n_records, const uint32_t* hit_mask, const uint32_t* big_list,
                            const uint32_t* big_count, uint32_t* tile_cursor,
                            DevStatus* status, unsigned long long* comp, hipStream_t st);
@@ -272,8 +274,9 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.pub.off_ranges = take(8 * n_tiles);
   l.pub.off_ncontrib = take(4 * n_pix);
   l.pub.off_grad2d = take(uint64_t(kGradFloats) * 4 * n_rec);
+  l.pub.off_live = take(n_rec);
   l.off_tfinal_ws = take(4 * n_pix);
-  l.off_live = take(4 * n_prims);
+  l.off_kept = take(4 * n_prims);
   l.off_live_list = take(4 * n_list);
   l.off_live_count = take(4 * uint64_t(kKeptLists) * uint64_t(f->n_scenes > 0 ? f->n_scenes : 1));
   l.off_grad_compact = take(4 * n_grad_compact);
@@ -378,7 +381,8 @@ ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes, u
     bool used = false;
     for (const DevView& v : p.dv) used = used || v.scene == sc;
     if (!used || p.ds[sc].n == 0) continue;
-    const LiveOut kept{at<uint32_t>(ws, L.off_live) + p.ds[sc].prim_base,
+    const LiveOut kept{at<uint8_t>(ws, L.pub.off_live),
+                       at<uint32_t>(ws, L.off_kept) + p.ds[sc].prim_base,
                        at<uint32_t>(ws, L.off_offsets) + p.ds[sc].prim_base,
                        at<uint32_t>(ws, L.off_live_list) + p.ds[sc].list_base,
                        at<uint32_t>(ws, L.off_live_count) + size_t(sc) * kKeptLists,
@@ -418,9 +422,10 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
                              pre_partials_used(p), uint32_t(L.n_pre_partials), status, s));
   uint32_t* hit_mask = at<uint32_t>(ws, L.off_hit_mask);
   auto* slots = at<unsigned long long>(ws, L.off_slots);
-  UBS_HIP(launch_bin_count(records, views, frame->n_views, n_rec, tile_counts, hit_mask, big_list,
-                           big_count, slots, L.tile_slots, status, at<float>(ws, L.pub.off_grad2d),
-                           s));
+  const uint8_t* live = at<uint8_t>(ws, L.pub.off_live);
+  UBS_HIP(launch_bin_count(records, live, views, frame->n_views, n_rec, tile_counts, hit_mask,
+                           big_list, big_count, slots, L.tile_slots, status,
+                           at<float>(ws, L.pub.off_grad2d), s));
   stage_mark(frame, UBS_STAGE_BIN_COUNT, 1, s);
   stage_mark(frame, UBS_STAGE_SCAN, 0, s);
   // segment starts of the tiles; the total sets pairs_needed and overflow
@@ -428,8 +433,8 @@ ubs_status ubs_bin_sort(const ubs_frame* frame, void* ws, uint64_t ws_bytes, voi
                       at<uint32_t>(ws, L.off_tile_order), at<uint32_t>(ws, L.off_order_hist)));
   stage_mark(frame, UBS_STAGE_SCAN, 1, s);
   stage_mark(frame, UBS_STAGE_BIN_EMIT, 0, s);
-  UBS_HIP(launch_bin_emit(records, views, frame->n_views, n_rec, hit_mask, big_list, big_count,
-                          tile_cursor, status, comp, s));
+  UBS_HIP(launch_bin_emit(records, live, views, frame->n_views, n_rec, hit_mask, big_list,
+                          big_count, tile_cursor, status, comp, s));
   stage_mark(frame, UBS_STAGE_BIN_EMIT, 1, s);
   stage_mark(frame, UBS_STAGE_SORT, 0, s);
   UBS_HIP(launch_tile_sort(comp, slots, L.tile_slots, tile_counts, tile_cursor, status,
@@ -507,7 +512,8 @@ ubs_status ubs_render_bwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
     }
     // the adjoint runs only for the primitives some view kept (listed by
     // the forward preprocess)
-    const LiveIn kept{at<uint32_t>(ws, L.off_live) + p.ds[sc].prim_base,
+    const LiveIn kept{at<uint8_t>(ws, L.pub.off_live),
+                      at<uint32_t>(ws, L.off_kept) + p.ds[sc].prim_base,
                       at<uint32_t>(ws, L.off_offsets) + p.ds[sc].prim_base,
                       at<uint32_t>(ws, L.off_live_list) + p.ds[sc].list_base,
                       at<uint32_t>(ws, L.off_live_count) + size_t(sc) * kKeptLists,

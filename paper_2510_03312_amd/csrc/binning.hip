@@ -147,7 +147,7 @@ __device__ __forceinline__ uint32_t global_tile(const DevView& V, int tx, int ty
 constexpr int kBinRecPerWave = 256;
 constexpr int kBinWaves = 4;   // 256-thread workgroups
 
-__device__ __forceinline__ uint32_t gather_live(const float* __restrict__ records,
+__device__ __forceinline__ uint32_t gather_live(const uint8_t* __restrict__ live,
                                                 uint32_t n_records, uint32_t* __restrict__ list) {
   const int lane = threadIdx.x & 63;
   const uint32_t wave_global = blockIdx.x * kBinWaves + (threadIdx.x >> 6);
@@ -157,7 +157,7 @@ __device__ __forceinline__ uint32_t gather_live(const float* __restrict__ record
 #pragma unroll
   for (int m = 0; m < kBinRecPerWave / 64; ++m) {
     const uint32_t rec = base + uint32_t(m * 64 + lane);
-    const bool vis = rec < n_records && records[size_t(rec) * kRecFloats + 5] > 0.0f;
+    const bool vis = rec < n_records && live[rec] != 0;
     const unsigned long long mask = __ballot(vis);
     if (vis) list[cnt + uint32_t(__popcll(mask & lt_mask))] = rec;
     cnt += uint32_t(__popcll(mask));
@@ -212,6 +212,7 @@ __device__ __forceinline__ void store_slot(uint32_t tile, unsigned long long key
 // pass.  Larger records are binned at the end by the whole workgroup, one at
 // a time, and appended to big_list for the spill pass.
 __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict__ records,
+                                                        const uint8_t* __restrict__ live,
                                                         const DevView* __restrict__ views,
                                                         int n_views, uint32_t n_records,
                                                         uint32_t* __restrict__ tile_counts,
@@ -236,7 +237,7 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const float* __restrict_
   if (threadIdx.x == 0) s_nbig = 0u;
   __syncthreads();
   uint32_t* list = s_list[w];
-  const uint32_t cnt = gather_live(records, n_records, list);
+  const uint32_t cnt = gather_live(live, n_records, list);
   for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
     const bool active = c0 + lane < cnt;
     const uint32_t rec = active ? list[c0 + lane] : 0u;
@@ -346,6 +347,7 @@ __device__ __forceinline__ void emit_big_records(uint32_t block, uint32_t n_bloc
 // each segment's first slot and ends one past its last.  Without a spill
 // every workgroup returns at once.
 __global__ void __launch_bounds__(256) bin_emit_kernel(const float* __restrict__ records,
+                                                       const uint8_t* __restrict__ live,
                                                        const DevView* __restrict__ views,
                                                        int n_views, uint32_t n_records,
                                                        const uint32_t* __restrict__ hit_mask,
@@ -368,7 +370,7 @@ __global__ void __launch_bounds__(256) bin_emit_kernel(const float* __restrict__
   __shared__ uint32_t s_bits[kBinWaves][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   uint32_t* list = s_list[w];
-  const uint32_t cnt = gather_live(records, n_records, list);
+  const uint32_t cnt = gather_live(live, n_records, list);
   for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
     const bool active = c0 + lane < cnt;
     const uint32_t rec = active ? list[c0 + lane] : 0u;
@@ -520,13 +522,14 @@ static unsigned bin_blocks(uint32_t n_records) {
 constexpr unsigned kBigBlocks = 1024;
 
 // tile_counts and *big_count must be zero.
-hipError_t launch_bin_count(const float* records, const DevView* views, int n_views,
+hipError_t launch_bin_count(const float* records, const uint8_t* live, const DevView* views,
+                            int n_views,
                             uint32_t n_records, uint32_t* tile_counts, uint32_t* hit_mask,
                             uint32_t* big_list, uint32_t* big_count, unsigned long long* slots,
                             uint32_t slot_cap, DevStatus* status, float* grad2d, hipStream_t st) {
   if (n_records == 0) return hipSuccess;
   hipLaunchKernelGGL(bin_count_kernel, dim3(bin_blocks(n_records)), dim3(256), 0, st, records,
-                     views, n_views, n_records, tile_counts, hit_mask, big_list, big_count, slots,
+                     live, views, n_views, n_records, tile_counts, hit_mask, big_list, big_count, slots,
                      slot_cap, status, grad2d);
   return hipGetLastError();
 }
@@ -820,14 +823,15 @@ hipError_t launch_scan_compact(const uint32_t* flags, uint32_t n, uint32_t* tile
   return scan_impl(flags, n, tile_sums, offsets, list, nullptr, 0ull, st, total_out);
 }
 
-hipError_t launch_bin_emit(const float* records, const DevView* views, int n_views,
+hipError_t launch_bin_emit(const float* records, const uint8_t* live, const DevView* views,
+                           int n_views,
                            uint32_t n_records, const uint32_t* hit_mask, const uint32_t* big_list,
                            const uint32_t* big_count, uint32_t* tile_cursor,
                            DevStatus* status, unsigned long long* comp, hipStream_t st) {
   if (n_records == 0) return hipSuccess;
   const unsigned small_blocks = bin_blocks(n_records);
   hipLaunchKernelGGL(bin_emit_kernel, dim3(small_blocks + kBigBlocks), dim3(256), 0, st, records,
-                     views, n_views, n_records, hit_mask, big_list, big_count, small_blocks,
+                     live, views, n_views, n_records, hit_mask, big_list, big_count, small_blocks,
                      tile_cursor, status, comp);
   return hipGetLastError();
 }

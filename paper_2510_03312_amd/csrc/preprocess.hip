@@ -44,18 +44,16 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
         live = false;
       }
     }
-    if (!live) {
-      o0 = make_float4(0.f, 0.f, 0.f, 0.f);
-      o1 = make_float4(0.f, 0.f, 0.f, 0.f);
-      o2 = make_float4(0.f, 0.f, 0.f, 0.f);
-    } else {
-      ++visible;
-    }
+    // a culled record is marked only: its fields are not written
     const size_t rec = size_t(V.rec_base) + size_t(i);
-    float4* rp = reinterpret_cast<float4*>(records + rec * kRecFloats);
-    store_stream(&rp[0], o0);
-    store_stream(&rp[1], o1);
-    store_stream(&rp[2], o2);
+    kept.rec_live[rec] = live ? 1u : 0u;
+    if (live) {
+      ++visible;
+      float4* rp = reinterpret_cast<float4*>(records + rec * kRecFloats);
+      store_stream(&rp[0], o0);
+      store_stream(&rp[1], o1);
+      store_stream(&rp[2], o2);
+    }
   }
   const bool keep = active && visible > 0;
   if (active) kept.flags[i] = keep ? 1u : 0u;
@@ -162,9 +160,8 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int sce
     const DevView& V = views[v];
     if (V.scene != scene) continue;
     const size_t rec = size_t(V.rec_base) + size_t(i);
-    // the forward wrote rho > 0 exactly for the records it kept
+    if (!kept.rec_live[rec]) continue;
     const float* rp = records + rec * kRecFloats;
-    if (!(rp[5] > 0.0f)) continue;
     float gr[kGradFloats];
     float* gp = grad2d + rec * kGradFloats;
 #pragma unroll

@@ -107,6 +107,7 @@ __host__ __device__ constexpr uint32_t kept_list_cap(int64_t n) {
   return uint32_t(((n + 255) / 256 + kKeptLists - 1) / kKeptLists) * 256u;
 }
 struct LiveOut {
+  uint8_t* rec_live; // per record (all views), 1 if the record survived culling
   uint32_t* flags;   // per primitive, 1 if kept
   uint32_t* pos;
   uint32_t* list;    // kKeptLists lists of cap entries
@@ -114,6 +115,7 @@ struct LiveOut {
   uint32_t cap;
 };
 struct LiveIn {
+  const uint8_t* rec_live;
   const uint32_t* flags;
   const uint32_t* pos;
   const uint32_t* list;
@@ -160,7 +162,7 @@ struct Layout {
   uint64_t off_tfinal_ws;            // final transmittance kept for the adjoint
   uint64_t off_tile_order;   // the rasters' tile order (longest first)
   uint64_t off_order_hist;   // its per-workgroup bin counts (large frames)
-  uint64_t off_live, off_live_list, off_live_count;  // per-primitive live flags, compacted list, counts
+  uint64_t off_kept, off_live_list, off_live_count;  // per-primitive kept flags, kept lists, counts
   uint64_t off_grad_compact;         // adjoint output of live primitives, [F][n] per scene
   uint64_t off_pre_partials;         // per-workgroup preprocess counts [2][n_pre_partials]
   int64_t n_pre_partials;

@@ -174,7 +174,19 @@ class Renderer:
         return self.ws[off:off + count * esz].view(dtype)
 
     def records(self) -> torch.Tensor:
+        """The records in the workspace, [n_records][12] (a view: only the
+        live ones are written by the preprocess, see ``record_live``)."""
         return self.region(self.layout.off_records, 12 * self.layout.n_records, torch.float32).view(-1, 12)
+
+    def record_live(self) -> torch.Tensor:
+        """Per record, 1 if it survived culling (uint8 view)."""
+        return self.region(self.layout.off_live, self.layout.n_records, torch.uint8)
+
+    def live_records(self) -> torch.Tensor:
+        """A copy of the records with the culled ones zeroed."""
+        rec = self.records()
+        return torch.where(self.record_live().bool()[:, None], rec, torch.zeros((), dtype=rec.dtype,
+                                                                                device=rec.device))
 
     def grad2d(self) -> torch.Tensor:
         return self.region(self.layout.off_grad2d, 10 * self.layout.n_records, torch.float32).view(-1, 10)

@@ -26,6 +26,17 @@ def to_dev(a: np.ndarray) -> torch.Tensor:
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
+def live_records(r):
+    """The frame's records with the culled ones zeroed, after checking that
+    every record marked live has rho > 0 (the preprocess writes the fields
+    of the live records only)."""
+    live = r.record_live().cpu().numpy()
+    assert set(np.unique(live)) <= {0, 1}
+    rec = r.live_records().cpu().numpy()
+    assert (rec[live == 1, 5] > 0).all()
+    return rec
+
+
 def gpu_render(cfg: dict, tuning=None, *, want_grad: bool = False, d_images=None, l1: bool = False,
                d_tfinals=None, l1_targets=None):
     """Render every view of a workload on the GPU in one frame.  Backward
@@ -39,7 +50,7 @@ def gpu_render(cfg: dict, tuning=None, *, want_grad: bool = False, d_images=None
     out = {"renderer": r, "image_flat": image, "t_flat": tfin,
            "images": [x.cpu().numpy() for x in split_views(image, cfg["views"])],
            "t_final": [x.cpu().numpy() for x in split_views(tfin, cfg["views"])],
-           "status": r.status(), "records": r.records().cpu().numpy()}
+           "status": r.status(), "records": live_records(r)}
     if want_grad:
         if l1:
             tg = cfg["targets"] if l1_targets is None else l1_targets

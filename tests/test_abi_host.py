@@ -37,7 +37,7 @@ def test_library_exports_every_declared_entry_point():
 
 
 def test_abi_version_and_param_counts():
-    assert _lib.ubs_abi_version() == 1
+    assert _lib.ubs_abi_version() == 2
     for dim in (3, 6, 7, 8, 9, 10):
         for rot in (0, 1):
             assert _lib.ubs_param_count(dim, rot) == param_count(dim, rot)
@@ -58,7 +58,7 @@ def test_ctypes_structs_match_the_header(tmp_path):
         "ubs_frame": ["scenes", "n_scenes", "n_views", "views", "tuning", "stage_events"],
         "ubs_layout": ["bytes", "n_records", "n_tiles", "n_pixels", "pair_capacity", "key_bits",
                        "n_views", "off_status", "off_records", "off_keys", "off_values",
-                       "off_ranges", "off_ncontrib", "off_grad2d"],
+                       "off_ranges", "off_ncontrib", "off_grad2d", "off_live"],
         "ubs_status_block": ["pairs_needed", "overflow", "n_nonfinite", "n_visible", "sort_stalled",
                              "spill"],
         "ubs_adam": ["lr_mu_x", "lr_opacity", "lr_scale", "lr_other", "beta1", "beta2", "eps",
@@ -117,9 +117,10 @@ def test_size_query_without_gpu():
     assert lay.key_bits == 32 + 5
     assert lay.pair_capacity == 1 << 20
     offs = [lay.off_status, lay.off_records, lay.off_keys, lay.off_values, lay.off_ranges,
-            lay.off_ncontrib, lay.off_grad2d]
+            lay.off_ncontrib, lay.off_grad2d, lay.off_live]
     assert all(o % 256 == 0 for o in offs)
     assert lay.bytes >= lay.off_grad2d + 40 * 1000
+    assert lay.bytes >= lay.off_live + 1000
     # multi-view frames concatenate records, tiles and pixels
     cfg4 = make_config("cfg4", scene_sizes=(10, 20, 30, 40), n_views=6)
     lay4 = _lib.UbsLayout()

@@ -33,7 +33,8 @@ import numpy as np
 import pytest
 import torch
 
-from _gpu_common import (GRAD_BLOCKS, bin_reference, gpu_ready, grad_violations, log, to_dev)
+from _gpu_common import (GRAD_BLOCKS, bin_reference, gpu_ready, grad_violations, live_records, log,
+                         to_dev)
 from oracle import preprocess as opp
 from oracle import raster as oraster
 from oracle import render as orender
@@ -129,7 +130,7 @@ def full(request):
         "per_view": per_view, "rec_base": rec_base, "dimgs": dimgs, "d_dev": d_dev,
         "images": [x.cpu().numpy() for x in split_views(image, views)],
         "t_finals": [x.cpu().numpy() for x in split_views(t_final, views)],
-        "records": r.records().cpu().numpy(),
+        "records": live_records(r),
         "grad2d": r.grad2d().cpu().numpy() if dparams is not None else None,
         "dparams": [g.cpu().numpy() for g in dparams] if dparams is not None else None,
         "keys": keys.cpu().numpy().view(np.uint64),

@@ -65,6 +65,7 @@ def _inject_and_sort(cfg, recs, tile_slots=0):
     frame = r.make_frame(scenes, cfg["views"])
     r.preprocess(frame)
     r.records().copy_(to_dev(recs))
+    r.record_live().copy_(to_dev((recs[:, 5] > 0).astype(np.uint8)))
     r.bin_sort(frame)
     st = r.status()
     K = st["pairs_needed"]
@@ -203,6 +204,7 @@ def test_sort_paths_and_digit_widths_agree(digit_bits, n, W, H, ext, slots):
     frame = r.make_frame([SceneRef(to_dev(cfg["scenes"][0].params), 3, 0)], cfg["views"])
     r.preprocess(frame)
     r.records().copy_(to_dev(recs))
+    r.record_live().copy_(to_dev((recs[:, 5] > 0).astype(np.uint8)))
     r.bin_sort(frame)
     K = r.status()["pairs_needed"]
     assert K == sk.size

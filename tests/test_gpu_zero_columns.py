@@ -28,7 +28,7 @@ def _backward_twice(cfg, tuning=None):
         nan.append(g)
     r.render_bwd(frame, d, None, None, None)
     torch.cuda.synchronize()
-    rec = r.records().cpu().numpy()
+    rec = r.live_records().cpu().numpy()
     live = [np.zeros(s.n, dtype=bool) for s in cfg["scenes"]]
     base = 0
     for v in cfg["views"]:
