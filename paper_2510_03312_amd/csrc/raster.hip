@@ -414,10 +414,9 @@ __device__ __forceinline__ void raster_bwd_tile(
       {
         const FPair s0 = swap_rows(h[0], h[1]);   // rows: fields 0, 2, 1, 3
         const FPair s1 = swap_rows(h[2], h[3]);   // rows: fields 4, 6, 5, 7
-        const FPair s2 = swap_rows(h[4], h[4]);   // rows: fields 8, 8, 9, 9
         t3[0] = s0.a + s0.b;
         t3[1] = s1.a + s1.b;
-        t3[2] = s2.a + s2.b;
+        t3[2] = h[4];   // rows: fields 8, 8, 9, 9, each row a partial sum
       }
       // t3[0] and t3[1] share one register from here: pairs of lanes 8
       // apart are summed in each, half-rows take t3[0]'s (lanes 0-7) or
@@ -430,12 +429,19 @@ __device__ __forceinline__ void raster_bwd_tile(
       u += dpp_row<0x4E>(u);    // quad permutation [2, 3, 0, 1]
       u += dpp_row<0xB1>(u);    // quad permutation [1, 0, 3, 2]
       row_sum_all<1>(&t3[2]);
+      // rows 1 and 3 add the totals of rows 0 and 2 (DPP row broadcast of
+      // each row's lane 15 into the next row; rows 0 and 2 are not written):
+      // fields 8 and 9 complete.  (One DPP add: the compiler would build it
+      // from a move and an add.  The nop gives the two wait states a DPP
+      // read needs after the VALU write of its source.)
+      asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf"
+                   : "+v"(t3[2]));
       // keep the last DPP adds ahead of the branch (sunk into it, an add
       // could no longer take its operand through DPP)
       asm volatile("" : "+v"(u), "+v"(t3[2]));
       // one atomic instruction: lanes 7 + 8k add the eight totals of u, lanes
-      // 6 and 38 (rows 0 and 2 of t3[2]) fields 8 and 9
-      const bool lane_u = (lane & 7) == 7, lane_t = (lane & 31) == 6;
+      // 22 and 54 (rows 1 and 3 of t3[2]) fields 8 and 9
+      const bool lane_u = (lane & 7) == 7, lane_t = (lane & 31) == 22;
       if (lane_u || lane_t) {
         const int row = lane >> 4;
         const int sub = row == 1 ? 2 : (row == 2 ? 1 : row);
