@@ -57,6 +57,33 @@ def test_preprocess_records_match_oracle(case):
     assert g["status"]["n_nonfinite"] == 0
 
 
+def test_preprocess_writes_live_records_and_flags_only():
+    """ubs_preprocess writes a live flag for every record and the fields of
+    the live records only: culled rows keep what the workspace held (here a
+    NaN sentinel), live rows are finite with rho > 0, and the flags count
+    n_visible (totalled by the binning)."""
+    from paper_2510_03312_amd import Renderer, SceneRef
+    log("[preprocess] live flags")
+    cfg = _cfg("headline_7d_ragged")
+    r = Renderer()
+    scenes = [SceneRef(to_dev(s.params), s.dim, s.rot) for s in cfg["scenes"]]
+    frame = r.make_frame(scenes, cfg["views"])
+    r.preprocess(frame)   # (sizes the workspace)
+    r.records().fill_(float("nan"))
+    r.record_live().fill_(7)
+    r.preprocess(frame)
+    torch.cuda.synchronize()
+    live = r.record_live().cpu().numpy()
+    rec = r.records().cpu().numpy()
+    assert set(np.unique(live)) == {0, 1}
+    assert np.isfinite(rec[live == 1]).all() and (rec[live == 1, 5] > 0).all()
+    assert np.isnan(rec[live == 0]).all()
+    r.bin_sort(frame)   # (the binning totals the preprocess's counts)
+    assert r.status()["n_visible"] == int(live.sum())
+    o = oracle_view(cfg, 0)
+    assert ((live == 1) != o["valid"])[~o["amb"]].sum() == 0
+
+
 # ------------------------------------------------------------------ bin + sort
 def _inject_and_sort(cfg, recs, tile_slots=0):
     from paper_2510_03312_amd import Renderer, SceneRef, Tuning
