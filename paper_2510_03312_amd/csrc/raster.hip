@@ -128,7 +128,8 @@ __device__ __forceinline__ void raster_fwd_tile(
       }
     }
     __syncthreads();
-    const int nb = int(min(uint32_t(BATCH), end - b0));
+    // (wavefront-uniform: the record loop runs on scalar counters)
+    const int nb = __builtin_amdgcn_readfirstlane(int(min(uint32_t(BATCH), end - b0)));
     for (int j = 0; j < nb; ++j) {
       const float4 g0 = s0[j], g1 = s1[j], g2 = s2[j];
       const ColTerms ct = col_terms(g0, fx - g0.x);
