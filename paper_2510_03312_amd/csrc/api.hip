@@ -175,7 +175,7 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   if (tu.pair_capacity < 0 || tu.pair_capacity > int64_t(1) << 30) return UBS_ERR_ARG;
   ds->clear();
   dv->clear();
-  uint64_t n_prims = 0, n_grad_compact = 0, n_list = 0;
+  uint64_t n_prims = 0, n_grad_compact = 0, n_par_compact = 0, n_list = 0;
   for (int s = 0; s < f->n_scenes; ++s) {
     const ubs_scene& S = f->scenes[s];
     if (S.dim < 3 || S.dim > kMaxDim) return UBS_ERR_ARG;
@@ -198,6 +198,9 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
     // the adjoint's compacted gradients: F rows of one column per kept-list entry
     const uint64_t n_compact = uint64_t(d.F) * kKeptLists * kept_list_cap(S.n);
     n_grad_compact = n_grad_compact > n_compact ? n_grad_compact : n_compact;
+    // and the kept primitives' parameters in the same layout, every scene's
+    d.par_base = int64_t(n_par_compact);
+    n_par_compact += n_compact;
     if (n_prims > 0x7fffffffull) return UBS_ERR_UNSUPPORTED;
     ds->push_back(d);
   }
@@ -280,6 +283,7 @@ static ubs_status plan(const ubs_frame* f, Layout* L, std::vector<DevView>* dv,
   l.off_live_list = take(4 * n_list);
   l.off_live_count = take(4 * uint64_t(kKeptLists) * uint64_t(f->n_scenes > 0 ? f->n_scenes : 1));
   l.off_grad_compact = take(4 * n_grad_compact);
+  l.off_par_compact = take(4 * n_par_compact);
   // per-workgroup counts of the preprocess launches (one launch per scene)
   // a multiple of 4, so that both halves of the table are 16-byte aligned
   l.n_pre_partials = int64_t((n_prims / 256 + uint64_t(f->n_scenes) + 1 + 3) & ~uint64_t(3));
@@ -386,7 +390,8 @@ ubs_status ubs_preprocess(const ubs_frame* frame, void* ws, uint64_t ws_bytes, u
                        at<uint32_t>(ws, L.off_offsets) + p.ds[sc].prim_base,
                        at<uint32_t>(ws, L.off_live_list) + p.ds[sc].list_base,
                        at<uint32_t>(ws, L.off_live_count) + size_t(sc) * kKeptLists,
-                       kept_list_cap(p.ds[sc].n)};
+                       kept_list_cap(p.ds[sc].n),
+                       at<float>(ws, L.off_par_compact) + p.ds[sc].par_base};
     UBS_HIP(launch_preprocess_fwd(fp64, p.ds[sc], sc, views, frame->n_views, records, kept,
                                   partial + block_base, stride, s));
     block_base += uint32_t((p.ds[sc].n + 255) / 256);
@@ -517,7 +522,8 @@ ubs_status ubs_render_bwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
                       at<uint32_t>(ws, L.off_offsets) + p.ds[sc].prim_base,
                       at<uint32_t>(ws, L.off_live_list) + p.ds[sc].list_base,
                       at<uint32_t>(ws, L.off_live_count) + size_t(sc) * kKeptLists,
-                      kept_list_cap(p.ds[sc].n)};
+                      kept_list_cap(p.ds[sc].n),
+                      at<float>(ws, L.off_par_compact) + p.ds[sc].par_base};
     UBS_HIP(launch_preprocess_bwd(fp64, p.ds[sc], sc, views, frame->n_views,
                                   at<float>(ws, L.pub.off_records), grad2d, kept,
                                   at<float>(ws, L.off_grad_compact), s));

@@ -3,7 +3,10 @@
 // (gradients of the records, summed over views -> gradients of every
 // parameter).  One lane per primitive; a lane reads its parameters once
 // (component-major rows, so a wavefront's loads of one row are contiguous)
-// and loops over the views of its scene.
+// and loops over the views of its scene.  The forward pass also copies the
+// parameter rows of the primitives some view kept to a compacted copy laid
+// out like the adjoint's work lists, so that the adjoint reads dense rows
+// instead of gathering a fifth of every line of the parameter array.
 #include "prim_math.hpp"
 
 namespace ubs {
@@ -15,13 +18,22 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
                                                              LiveOut kept,
                                                              uint32_t* __restrict__ partial,
                                                              uint32_t partial_stride) {
+  constexpr int F = param_rows(C, ROT).F;
+  // the workgroup's parameters, kept for the copy of its kept primitives
+  __shared__ float s_par[F][256];
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   const bool active = i < S.n;
   bool finite = true;
   Raw<C, ROT> r;
   Geo<T, C, ROT> g;
   if (active) {
-    load_raw<C, ROT>(S.params, S.n, i, r);
+    load_raw_rows<C, ROT>(
+        [&](int k) {
+          const float x = __builtin_nontemporal_load(&S.params[int64_t(k) * S.n + i]);
+          s_par[k][threadIdx.x] = x;
+          return x;
+        },
+        r);
     finite = r.finite;
     geo_forward<T, C, ROT>(r, g, S.variant);
   }
@@ -60,9 +72,10 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
   // per-workgroup counts (no atomics on a shared word per wavefront: those
   // serialise across the chip); the binning's first kernel adds them into
   // the status block.  The kept primitives go to the adjoint's list: one
-  // atomic per workgroup reserves their run (ascending inside it), and only
-  // the first wavefront waits for it, the others end here.
-  __shared__ uint32_t s_cnt[2];
+  // atomic per workgroup reserves their run (ascending inside it), and each
+  // wavefront then lists its own kept primitives and copies their parameter
+  // rows (from LDS) to their columns of the compacted copy.
+  __shared__ uint32_t s_cnt[2], s_run;
   __shared__ unsigned long long s_keep[4];
   if (threadIdx.x == 0) { s_cnt[0] = 0; s_cnt[1] = 0; }
   __syncthreads();
@@ -78,30 +91,28 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
     s_keep[wave] = km;
   }
   __syncthreads();
-  if (wave != 0) return;
   const unsigned long long m0 = s_keep[0], m1 = s_keep[1], m2 = s_keep[2], m3 = s_keep[3];
-  const uint32_t n_keep = uint32_t(__popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3));
   const uint32_t which = blockIdx.x % kKeptLists;
-  uint32_t base = 0;
-  if (lane == 0) {
+  if (threadIdx.x == 0) {
+    const uint32_t n_keep = uint32_t(__popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3));
     partial[blockIdx.x] = s_cnt[1];
     partial[partial_stride + blockIdx.x] = s_cnt[0];
-    if (n_keep) base = atomicAdd(&kept.count[which], n_keep);
+    s_run = n_keep ? atomicAdd(&kept.count[which], n_keep) : 0u;
   }
-  base = uint32_t(__shfl(int(base), 0, 64));
-  uint32_t* list = kept.list + size_t(which) * kept.cap;
-  const unsigned long long lt = (1ull << lane) - 1ull;
-  const int64_t i0 = int64_t(blockIdx.x) * 256 + lane;
+  __syncthreads();
+  if (!keep) return;
+  // entry q of the run: the kept primitives in thread order
+  uint32_t q = uint32_t(__popcll(km & ((1ull << lane) - 1ull)));
+  if (wave > 0) q += uint32_t(__popcll(m0));
+  if (wave > 1) q += uint32_t(__popcll(m1));
+  if (wave > 2) q += uint32_t(__popcll(m2));
+  const uint32_t p = s_run + q;
+  kept.list[size_t(which) * kept.cap + p] = uint32_t(i);
+  kept.pos[i] = p;
+  float* par = kept.par + size_t(which) * kept.cap + p;
+  const int64_t par_stride = int64_t(kKeptLists) * kept.cap;
 #pragma unroll
-  for (int w = 0; w < 4; ++w) {
-    const unsigned long long m = w == 0 ? m0 : (w == 1 ? m1 : (w == 2 ? m2 : m3));
-    if ((m >> lane) & 1ull) {
-      const uint32_t p = base + uint32_t(__popcll(m & lt));
-      list[p] = uint32_t(i0 + 64 * w);
-      kept.pos[i0 + 64 * w] = p;
-    }
-    base += uint32_t(__popcll(m));
-  }
+  for (int k = 0; k < F; ++k) par[k * par_stride] = s_par[k][threadIdx.x];
 }
 
 // The backward raster leaves per record the pixel sums of
@@ -130,9 +141,10 @@ __device__ __forceinline__ void record_gradient_from_sums(const float* __restric
 }
 
 // One thread per entry of the kept lists: the adjoint of the primitive at
-// entry e of list l, its gradient written to column t = l cap + e of the
-// compacted [F][kKeptLists cap] buffer (coalesced); scatter_dparams_kernel
-// moves it to the primitive's column.
+// entry e of list l, its parameters read from column t = l cap + e of the
+// compacted copy and its gradient written to column t of the compacted
+// [F][kKeptLists cap] buffer (both coalesced); scatter_dparams_kernel moves
+// it to the primitive's column.
 template <typename T, int C, int ROT>
 __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int scene,
                                                              const DevView* __restrict__ views,
@@ -150,8 +162,10 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int sce
   const uint32_t t = lo * kept.cap + pos;
   if (pos >= kept.count[lo]) return;
   const int64_t i = kept.list[t];
+  const int64_t stride = int64_t(kKeptLists) * kept.cap;
   Raw<C, ROT> r;
-  load_raw<C, ROT>(S.params, S.n, i, r);
+  // (dense rows of the compacted copy the preprocess wrote)
+  load_raw<C, ROT>(kept.par, stride, t, r);
   Geo<T, C, ROT> g;
   geo_forward<T, C, ROT>(r, g, S.variant);
   GeoGrad<T, C> G;
@@ -176,7 +190,6 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int sce
   constexpr int F = param_rows(C, ROT).F;
   float out[F];
   geo_backward<T, C, ROT>(r, g, G, out);
-  const int64_t stride = int64_t(kKeptLists) * kept.cap;
 #pragma unroll
   for (int k = 0; k < F; ++k) compact[int64_t(k) * stride + t] = out[k];
 }

@@ -60,14 +60,14 @@ struct Raw {
   bool finite;  // every loaded parameter is finite
 };
 
-template <int C, int ROT>
-__device__ __forceinline__ void load_raw(const float* __restrict__ P, int64_t n, int64_t i,
-                                         Raw<C, ROT>& r) {
+// A primitive's parameters from get(row), the value in parameter row `row`
+// (finite: every value read is finite).
+template <int C, int ROT, typename Get>
+__device__ __forceinline__ void load_raw_rows(Get get, Raw<C, ROT>& r) {
   const ParamRows pr = param_rows(C, ROT);
   bool fin = true;
-  // streaming loads: each parameter is read once per launch
   auto ld = [&](int row) {
-    const float x = __builtin_nontemporal_load(&P[int64_t(row) * n + i]);
+    const float x = get(row);
     fin = fin && isfinite(x);
     return x;
   };
@@ -95,6 +95,15 @@ __device__ __forceinline__ void load_raw(const float* __restrict__ P, int64_t n,
 #pragma unroll
   for (int k2 = 0; k2 < 3; ++k2) r.rgb[k2] = ld(pr.rgb + k2);
   r.finite = fin;
+}
+
+// Primitive i of the component-major array P (row stride n), with streaming
+// loads: each parameter is read once per launch.
+template <int C, int ROT>
+__device__ __forceinline__ void load_raw(const float* __restrict__ P, int64_t n, int64_t i,
+                                         Raw<C, ROT>& r) {
+  load_raw_rows<C, ROT>(
+      [&](int row) { return __builtin_nontemporal_load(&P[int64_t(row) * n + i]); }, r);
 }
 
 // View-independent quantities of a primitive.

@@ -45,6 +45,7 @@ struct DevScene {
   uint32_t variant;    // UBS_TUNE_NO_BETA_* bits of the frame (Sec. 5.3 ablations)
   int64_t prim_base;   // first entry of this scene in per-primitive tables
   int64_t list_base;   // first entry of this scene's kept lists
+  int64_t par_base;    // first float of this scene's compacted parameter copy
 };
 
 // Row offsets of the parameter format (component-major [F][n]).
@@ -99,8 +100,11 @@ __host__ __device__ constexpr bool dim_ok(int dim) {
 // entries (cap = kept_list_cap(n)), with `count` entries per list; pos is a
 // kept primitive's index inside its list.  The adjoint runs one thread per
 // list entry, entry e of list l being column l cap + e of its compacted
-// gradient buffer (the columns past a list's count are unused).  (Several
-// counters spread the workgroups' reserving atomics over several
+// gradient buffer (the columns past a list's count are unused); the
+// preprocess also copies the kept primitive's parameter rows to that column
+// of `par` ([F][kKeptLists cap], per scene), so that the adjoint reads dense
+// rows instead of gathering a fifth of every line of the parameter array.
+// (Several counters spread the workgroups' reserving atomics over several
 // addresses.)
 constexpr uint32_t kKeptLists = 64;
 __host__ __device__ constexpr uint32_t kept_list_cap(int64_t n) {
@@ -113,6 +117,7 @@ struct LiveOut {
   uint32_t* list;    // kKeptLists lists of cap entries
   uint32_t* count;   // kKeptLists counters, zeroed before the preprocess launch
   uint32_t cap;
+  float* par;        // compacted parameter copy, [F][kKeptLists cap]
 };
 struct LiveIn {
   const uint8_t* rec_live;
@@ -121,6 +126,7 @@ struct LiveIn {
   const uint32_t* list;
   const uint32_t* count;
   uint32_t cap;
+  const float* par;
 };
 
 
@@ -164,6 +170,7 @@ struct Layout {
   uint64_t off_order_hist;   // its per-workgroup bin counts (large frames)
   uint64_t off_kept, off_live_list, off_live_count;  // per-primitive kept flags, kept lists, counts
   uint64_t off_grad_compact;         // adjoint output of live primitives, [F][n] per scene
+  uint64_t off_par_compact;          // kept primitives' parameters, [F][n] for each scene
   uint64_t off_pre_partials;         // per-workgroup preprocess counts [2][n_pre_partials]
   int64_t n_pre_partials;
   int64_t n_prims;                   // sum over scenes of primitives
