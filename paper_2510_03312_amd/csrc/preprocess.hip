@@ -126,10 +126,9 @@ __global__ void __launch_bounds__(256) preprocess_fwd_kernel(DevScene S, int sce
 //   d/d mx = 2 beta (a P + b Q), d/d my = 2 beta (b P + c Q),
 //   d/d a = -beta U, d/d b = -2 beta V, d/d c = -beta E,
 //   d/d o = A_o / o, d/d beta = ln 2 A_b
-// (in place; rec: the record as the raster used it).
-__device__ __forceinline__ void record_gradient_from_sums(const float* __restrict__ rec,
-                                                          float* g) {
-  const float a = rec[2], b = rec[3], c = rec[4], o = rec[6], beta = rec[7];
+// (in place; rf: fields 2-7 of the record as the raster used it).
+__device__ __forceinline__ void record_gradient_from_sums(const float* rf, float* g) {
+  const float a = rf[0], b = rf[1], c = rf[2], o = rf[4], beta = rf[5];
   const float P = g[0], Q = g[1], U = g[2], V = g[3], E = g[4];
   g[0] = 2.0f * beta * (a * P + b * Q);
   g[1] = 2.0f * beta * (b * P + c * Q);
@@ -174,13 +173,23 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(DevScene S, int sce
     const DevView& V = views[v];
     if (V.scene != scene) continue;
     const size_t rec = size_t(V.rec_base) + size_t(i);
-    if (!kept.rec_live[rec]) continue;
+    // the record's sums and fields are read together with its live flag
+    // (every row lies inside the workspace; a culled record's are unused)
+    const bool live = kept.rec_live[rec] != 0;
     const float* rp = records + rec * kRecFloats;
-    float gr[kGradFloats];
+    float gr[kGradFloats], rf[6];
     float* gp = grad2d + rec * kGradFloats;
 #pragma unroll
     for (int k = 0; k < kGradFloats; ++k) gr[k] = gp[k];
-    record_gradient_from_sums(rp, gr);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) rf[k] = rp[2 + k];
+    // (the loads stay ahead of the branch: one wait for all three)
+#pragma unroll
+    for (int k = 0; k < kGradFloats; ++k) asm volatile("" : "+v"(gr[k]));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) asm volatile("" : "+v"(rf[k]));
+    if (!live) continue;
+    record_gradient_from_sums(rf, gr);
 #pragma unroll
     for (int k = 0; k < 7; ++k) gp[k] = gr[k];
     ViewState<T, C> s;
