@@ -317,7 +317,10 @@ ubs_status ubs_render_fwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
  *            L1 mean |image - target| over all channels of all views, whose
  *            image gradient sign(image - target) / (3 sum_v H_v W_v) (sign 0
  *            at 0) is formed in-kernel; d_image and d_t_final must be NULL.
- * Writes every scenes[s].dparams (must be non-NULL).
+ * Writes every scenes[s].dparams (must be non-NULL).  The gradient is taken
+ * at the parameters ubs_preprocess read: the workspace keeps a copy of the
+ * parameters of every primitive with a live record, and this call reads
+ * that copy, not scenes[s].params.
  */
 ubs_status ubs_render_bwd(const ubs_frame* frame, void* ws, uint64_t ws_bytes,
                           const float* d_image, const float* d_t_final,

@@ -601,3 +601,29 @@ def test_second_backward_of_one_frame_gives_the_same_gradients():
     r.forward([SceneRef(to_dev(sc.params), sc.dim, sc.rot)], cfg["views"])
     (g3,) = r.backward(d)
     assert grad_violations(g3.cpu().numpy(), g1.astype(np.float64), rtol=1e-4, floor=1e-3).sum() == 0
+
+
+def test_backward_takes_the_gradient_at_the_parameters_the_preprocess_read():
+    """ubs_render_bwd reads the workspace's copy of the parameters of the
+    primitives with a live record, which ubs_preprocess wrote: overwriting
+    the caller's parameters (here with NaN) between the forward and the
+    backward pass changes no gradient, and the primitives without a live
+    record get zero."""
+    from paper_2510_03312_amd import Renderer, SceneRef
+    log("[bwd] parameters overwritten after the forward")
+    cfg = make_config("headline", n=20000, width=200, height=120)
+    sc = cfg["scenes"][0]
+    d = to_dev(np.random.default_rng(3).normal(size=(200 * 120, 3)).astype(np.float32))
+    r = Renderer()
+    r.forward([SceneRef(to_dev(sc.params), sc.dim, sc.rot)], cfg["views"])
+    (g1,) = r.backward(d)
+    g1 = g1.cpu().numpy()
+    p = to_dev(sc.params)
+    r.forward([SceneRef(p, sc.dim, sc.rot)], cfg["views"])
+    p.fill_(float("nan"))
+    (g2,) = r.backward(d)
+    g2 = g2.cpu().numpy()
+    assert np.isfinite(g2).all()
+    assert grad_violations(g2, g1.astype(np.float64), rtol=1e-4, floor=1e-3).sum() == 0
+    dead = ~np.abs(g1).any(axis=0)
+    assert dead.any() and (g2[:, dead] == 0).all()
